@@ -1,0 +1,320 @@
+"""Seeded synthetic inputs: mechanisms and per-cell reactor states.
+
+This module is shared by the GPU library's tests/bench and by the CPU oracle's
+tests.  It holds none of the integration method's arithmetic: it draws random
+numbers, checks integer atom balance while drawing reactions, and writes the
+mechanism text format that both sides parse on their own.
+
+Mechanism generator G(S, R, E, seed)
+-------------------------------------
+The paper states the kinetics only as a mechanism of N species and M
+reactions with forward/backward stoichiometric coefficients (Sec. 2.1, Eq. 1)
+and rates of progress built from rate constants (Eq. 2); its own mechanisms
+(n-dodecane, methane, n-heptane) are not available, so a synthetic family of
+the same structure stands in:
+
+* E elements taken in the order H, C, O, N (masses in g/mol).
+* S species; atom counts per element drawn uniformly from {0..3}, an all-zero
+  vector is redrawn.  The last species (index S-1) is inert: it takes part in
+  no reaction but collides as a third body.
+* Linear heat capacity per species, cp/R = a0 + a1*T, a0 ~ U[2.5, 6],
+  a1 ~ U[0, 1e-3] 1/K; formation enthalpy h_f ~ U[-3e5, 3e5] J/mol and
+  standard entropy s0 ~ U[150, 250] J/(mol K), both at 298.15 K.
+* R reversible reactions with 1-2 reactants and 1-2 products drawn from the
+  reactive species (repeats allowed, e.g. 2A), atom balanced.  All balanced
+  candidate reactions are enumerated; if fewer than R exist the whole species
+  set is redrawn from the same stream.  R distinct candidates are picked
+  without replacement and each is oriented by a fair coin.
+* log10 A ~ U[8, 14] (mol, cm, s units), b ~ U[-1, 2], Ea ~ U[0, 40] kcal/mol.
+* Exactly round(0.2 R) reactions, picked uniformly, are third-body reactions
+  with unit efficiencies for every species.
+
+Mechanism text format (version 1), one record per line, '#' starts a comment::
+
+    chem-mech 1
+    ELEMENTS <E>
+    <symbol> <mass g/mol>                                  (E lines)
+    SPECIES <S>
+    <name> <inert 0|1> <n_e0> .. <n_e(E-1)> <a0> <a1> <hf J/mol> <s0 J/mol/K>
+    REACTIONS <R>
+    <rev 0|1> <type 0|1|2> <nr> <r_1..r_nr> <np> <p_1..p_np> <A> <b> <Ea kcal/mol> [<A0> <b0> <Ea0>]
+    END
+
+type 0 = elementary, 1 = third body (+M, unit efficiencies), 2 = Lindemann
+falloff (+M) whose low-pressure limit (A0, b0, Ea0) follows.  Reactant and
+product lists hold 0-based species indices, a repeated index meaning a
+stoichiometric coefficient of 2 (at most 3 entries per side).  Floats are
+written with 17 significant digits so that every parser reads back the same
+doubles.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+ELEMENT_TABLE: Tuple[Tuple[str, float], ...] = (
+    ("H", 1.008), ("C", 12.011), ("O", 15.999), ("N", 14.007))
+
+P_ATM = 101325.0  # Pa
+
+
+@dataclasses.dataclass
+class Reaction:
+    reactants: List[int]
+    products: List[int]
+    A: float
+    b: float
+    Ea: float                 # kcal/mol
+    reversible: bool = True
+    kind: int = 0             # 0 elementary, 1 third body, 2 Lindemann falloff
+    low: Optional[Tuple[float, float, float]] = None   # (A0, b0, Ea0 kcal/mol)
+
+
+@dataclasses.dataclass
+class Mechanism:
+    elements: List[Tuple[str, float]]
+    names: List[str]
+    atoms: np.ndarray         # [S, E] int
+    a0: np.ndarray
+    a1: np.ndarray
+    hf: np.ndarray
+    s0: np.ndarray
+    inert: np.ndarray         # [S] bool
+    reactions: List[Reaction]
+    label: str = ""
+
+    @property
+    def n_species(self) -> int:
+        return len(self.names)
+
+    @property
+    def n_reactions(self) -> int:
+        return len(self.reactions)
+
+    def to_text(self) -> str:
+        return write_mechanism(self)
+
+
+def _f(x: float) -> str:
+    return repr(float(x)) if math.isfinite(x) else "nan"
+
+
+def write_mechanism(m: Mechanism) -> str:
+    out = [f"chem-mech 1", f"# {m.label}" if m.label else "# synthetic mechanism",
+           f"ELEMENTS {len(m.elements)}"]
+    for sym, mass in m.elements:
+        out.append(f"{sym} {_f(mass)}")
+    out.append(f"SPECIES {m.n_species}")
+    for k, name in enumerate(m.names):
+        atoms = " ".join(str(int(v)) for v in m.atoms[k])
+        out.append(f"{name} {int(bool(m.inert[k]))} {atoms} {_f(m.a0[k])} {_f(m.a1[k])} "
+                   f"{_f(m.hf[k])} {_f(m.s0[k])}")
+    out.append(f"REACTIONS {m.n_reactions}")
+    for r in m.reactions:
+        fields = [str(int(r.reversible)), str(int(r.kind)), str(len(r.reactants))]
+        fields += [str(int(i)) for i in r.reactants]
+        fields += [str(len(r.products))] + [str(int(i)) for i in r.products]
+        fields += [_f(r.A), _f(r.b), _f(r.Ea)]
+        if r.kind == 2:
+            assert r.low is not None
+            fields += [_f(v) for v in r.low]
+        out.append(" ".join(fields))
+    out.append("END")
+    return "\n".join(out) + "\n"
+
+
+def _balanced_pool(atoms: np.ndarray, reactive: int) -> List[Tuple[Tuple[int, ...], Tuple[int, ...]]]:
+    """All unordered pairs {left side, right side} of 1-2 reactive species with
+    equal integer atom vectors and different multisets."""
+    sides: List[Tuple[int, ...]] = [(i,) for i in range(reactive)]
+    sides += [(i, j) for i in range(reactive) for j in range(i, reactive)]
+    groups = {}
+    for s in sides:
+        key = tuple(int(v) for v in atoms[list(s)].sum(axis=0))
+        groups.setdefault(key, []).append(s)
+    pool = []
+    for key in sorted(groups):
+        members = groups[key]
+        for a in range(len(members)):
+            for b in range(a + 1, len(members)):
+                pool.append((members[a], members[b]))
+    return pool
+
+
+def make_mechanism(S: int, R: int, E: int, seed: int, max_redraws: int = 1000) -> Mechanism:
+    """G(S, R, E, seed): see the module docstring for the recipe and draw order."""
+    if not (2 <= S <= 63 and 1 <= E <= len(ELEMENT_TABLE) and R >= 1):
+        raise ValueError("unsupported G(S,R,E)")
+    rng = np.random.default_rng(seed)
+    elements = list(ELEMENT_TABLE[:E])
+    for _attempt in range(max_redraws):
+        atoms = np.zeros((S, E), dtype=np.int64)
+        for k in range(S):
+            while True:
+                v = rng.integers(0, 4, size=E)
+                if v.sum() > 0:
+                    break
+            atoms[k] = v
+        pool = _balanced_pool(atoms, S - 1)
+        if len(pool) >= R:
+            break
+    else:
+        raise RuntimeError(f"G({S},{R},{E},{seed}): no balanced reaction set after {max_redraws} redraws")
+    a0 = rng.uniform(2.5, 6.0, size=S)
+    a1 = rng.uniform(0.0, 1e-3, size=S)
+    hf = rng.uniform(-3e5, 3e5, size=S)
+    s0 = rng.uniform(150.0, 250.0, size=S)
+    pick = rng.choice(len(pool), size=R, replace=False)
+    flip = rng.integers(0, 2, size=R)
+    log10A = rng.uniform(8.0, 14.0, size=R)
+    b = rng.uniform(-1.0, 2.0, size=R)
+    Ea = rng.uniform(0.0, 40.0, size=R)
+    n_tb = int(round(0.2 * R))
+    tb = set(int(i) for i in rng.choice(R, size=n_tb, replace=False))
+    reactions = []
+    for j in range(R):
+        left, right = pool[int(pick[j])]
+        if flip[j]:
+            left, right = right, left
+        reactions.append(Reaction(list(left), list(right), float(10.0 ** log10A[j]),
+                                  float(b[j]), float(Ea[j]), True, 1 if j in tb else 0))
+    inert = np.zeros(S, dtype=bool)
+    inert[S - 1] = True
+    names = [f"S{k}" for k in range(S - 1)] + ["INERT"]
+    return Mechanism(elements, names, atoms, a0, a1, hf, s0, inert, reactions,
+                     label=f"G({S},{R},{E},seed {seed})")
+
+
+# ---------------------------------------------------------------- states ----
+
+def composition(rng: np.random.Generator, S: int, alpha: float, n: int = 1,
+                inert_fraction: float = 0.7) -> np.ndarray:
+    """[S, n] mass fractions: the inert species holds `inert_fraction`, the
+    reactive species share the rest by a Dirichlet(alpha) draw per column; a
+    final division by the column sum only removes rounding."""
+    Y = np.empty((S, n))
+    d = rng.dirichlet(np.full(S - 1, alpha), size=n).T     # [S-1, n]
+    Y[:S - 1] = (1.0 - inert_fraction) * d
+    Y[S - 1] = inert_fraction
+    Y /= Y.sum(axis=0, keepdims=True)
+    return Y
+
+
+@dataclasses.dataclass
+class Workload:
+    """One batch of reactor cells (SoA: Y[k, i] species-major)."""
+    mech: Mechanism
+    T: np.ndarray           # [n]
+    Y: np.ndarray           # [S, n]
+    p: float
+    dt: float
+    rtol: float
+    atol: float
+    name: str = ""
+    shape: Optional[Tuple[int, ...]] = None
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.T.shape[0])
+
+
+def uniform_batch(mech: Mechanism, n: int, seed: int, T_lo: float, T_hi: float,
+                  dt: float, rtol: float, atol: float, alpha: float = 1.0,
+                  name: str = "") -> Workload:
+    """n cells with T ~ U[T_lo, T_hi] and Y = 0.7 inert + 0.3 Dirichlet(alpha)."""
+    rng = np.random.default_rng(seed)
+    T = rng.uniform(T_lo, T_hi, size=n)
+    Y = composition(rng, mech.n_species, alpha, n)
+    return Workload(mech, T, np.ascontiguousarray(Y), P_ATM, dt, rtol, atol, name=name)
+
+
+def flame_profile(mech: Mechanism, shape: Tuple[int, int, int], seed: int, Y_eq: np.ndarray,
+                  dt: float, rtol: float, atol: float, name: str = "",
+                  x_centre: float = 128.0, width: float = 8.0, noise_K: float = 5.0) -> Workload:
+    """A planar tanh flame through a box of nx*ny*nz cells.
+
+    x is the integer index along the longest (slowest-varying) axis, the cell
+    order being i = z + nz*(y + ny*x).  w = (1 + tanh((x - x_centre)/width))/2,
+    T = 300 + 1900 w + N(0, noise_K) per cell, Y = (1 - w) Y_cold + w Y_eq
+    where Y_cold is one Dirichlet(2) draw over the reactive species with 0.7
+    inert (drawn first from the stream) and Y_eq is the equilibrium
+    composition supplied by the caller."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(seed)
+    Y_cold = cold_mixture(rng, mech.n_species)
+    n = nx * ny * nz
+    x = np.repeat(np.arange(nx, dtype=np.float64), ny * nz)
+    w = 0.5 * (1.0 + np.tanh((x - x_centre) / width))
+    T = 300.0 + 1900.0 * w + rng.normal(0.0, noise_K, size=n)
+    Y = (1.0 - w)[None, :] * Y_cold[:, None] + w[None, :] * np.asarray(Y_eq, dtype=np.float64)[:, None]
+    return Workload(mech, T, np.ascontiguousarray(Y), P_ATM, dt, rtol, atol, name=name, shape=shape)
+
+
+def cold_mixture(rng: np.random.Generator, S: int) -> np.ndarray:
+    """The unburnt mixture of the flame profile: 0.7 inert + 0.3 Dirichlet(2)."""
+    return composition(rng, S, 2.0, 1)[:, 0]
+
+
+@dataclasses.dataclass
+class Box:
+    L: int
+    T: np.ndarray
+    Y: np.ndarray
+    dt: float
+
+
+def amr_boxes(mech: Mechanism, n_boxes: int, seed: int, L_lo: int = 8, L_hi: int = 64,
+              T_lo: float = 900.0, T_hi: float = 2300.0, noise_K: float = 20.0,
+              dt_lo: float = 1e-7, dt_hi: float = 1e-5, max_cells: Optional[int] = None) -> List[Box]:
+    """Uneven cubic boxes: edge L = round(exp(U[ln L_lo, ln L_hi])); per box a
+    temperature T_b ~ U[T_lo, T_hi] plus N(0, noise_K) per cell, one
+    Dirichlet(1) composition with 0.7 inert, and dt_b log-uniform in
+    [dt_lo, dt_hi].  `max_cells` caps each box (for scaled-down runs)."""
+    rng = np.random.default_rng(seed)
+    boxes = []
+    for _ in range(n_boxes):
+        L = int(round(math.exp(rng.uniform(math.log(L_lo), math.log(L_hi)))))
+        n = L ** 3
+        if max_cells is not None:
+            n = min(n, max_cells)
+        Tb = rng.uniform(T_lo, T_hi)
+        Yb = composition(rng, mech.n_species, 1.0, 1)[:, 0]
+        dtb = math.exp(rng.uniform(math.log(dt_lo), math.log(dt_hi)))
+        T = Tb + rng.normal(0.0, noise_K, size=n)
+        Y = np.ascontiguousarray(np.repeat(Yb[:, None], n, axis=1))
+        boxes.append(Box(L, T, Y, dtb))
+    return boxes
+
+
+def poisson_trace(seed: int, rate_hz: float, duration_s: float) -> np.ndarray:
+    """Open-loop arrival times (s) with exponential inter-arrival gaps."""
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / rate_hz)
+        if t >= duration_s:
+            break
+        out.append(t)
+    return np.asarray(out)
+
+
+# --------------------------------------------------------- named configs ----
+
+CONFIG_MECH = {
+    1: (10, 25, 3, 0),
+    2: (10, 25, 3, 1),
+    3: (53, 325, 4, 2),
+    4: (30, 180, 4, 3),
+}
+
+
+def config_mechanism(cfg: int) -> Mechanism:
+    return make_mechanism(*CONFIG_MECH[cfg])
+
+
+def config_seed(cfg: int) -> int:
+    return 1000 + cfg

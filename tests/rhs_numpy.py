@@ -1,0 +1,74 @@
+"""A second, independent right-hand side in numpy (test helper).
+
+It reads the mechanism from the generator's data classes (not from either
+parser) and accepts complex states, so that complex-step differentiation of it
+gives the Jacobian to rounding (Squire & Trapp).  It is compared with the
+oracle's rhs value by value before its derivatives are trusted.
+"""
+import numpy as np
+
+RU = 8.31446261815324
+TREF = 298.15
+PATM = 101325.0
+
+
+def rhs(mech, y, p, fixed_T=False):
+    S = mech.n_species
+    Y = y[:S]
+    T = y[S]
+    W = mech.atoms @ np.array([m for _, m in mech.elements])
+    a0, a1, hf, s0 = mech.a0, mech.a1, mech.hf, mech.s0
+    H = hf + RU * (a0 * (T - TREF) + a1 * (T ** 2 - TREF ** 2) / 2)
+    Sm = s0 + RU * (a0 * np.log(T / TREF) + a1 * (T - TREF))
+    Cp = RU * (a0 + a1 * T)
+    G = H - T * Sm
+    # density in g/cm^3 and concentrations in mol/cm^3
+    Wbar = 1.0 / np.sum(Y / W)
+    rho = p * 10.0 * Wbar / (RU * 1e7 * T)
+    C = rho * Y / W
+    M = np.sum(C)
+    wdot = np.zeros(S, dtype=np.result_type(y, float))
+    for r in mech.reactions:
+        kinf = r.A * T ** r.b * np.exp(-r.Ea * 4184.0 / (RU * T))
+        kf = kinf
+        if r.kind == 2:
+            A0, b0, Ea0 = r.low
+            k0 = A0 * T ** b0 * np.exp(-Ea0 * 4184.0 / (RU * T))
+            Pr = k0 * M / kinf
+            kf = kinf * Pr / (1 + Pr)
+        pf = np.prod([C[i] for i in r.reactants])
+        pr = np.prod([C[i] for i in r.products])
+        if r.reversible:
+            nu = np.zeros(S)
+            for i in r.reactants:
+                nu[i] -= 1
+            for i in r.products:
+                nu[i] += 1
+            # equilibrium constant in pressure units, converted to mol/cm^3
+            Kp = np.exp(-np.sum(nu * G) / (RU * T))
+            Kc = Kp * (PATM / (RU * T) * 1e-6) ** np.sum(nu)
+            q = kf * pf - kf / Kc * pr
+        else:
+            q = kf * pf
+        if r.kind == 1:
+            q = q * M
+        for i in r.reactants:
+            wdot[i] -= q
+        for i in r.products:
+            wdot[i] += q
+    f = np.zeros(S + 1, dtype=np.result_type(y, float))
+    f[:S] = W * wdot / rho
+    f[S] = 0.0 if fixed_T else -np.sum(H * wdot) / np.sum(C * Cp)
+    return f
+
+
+def jac_complex_step(mech, y, p, fixed_T=False, h=1e-30):
+    """J[i, j] = Im f(y + i h e_j) / h (|h| * |y| far below rounding)."""
+    n = y.shape[0]
+    J = np.zeros((n, n))
+    for j in range(n):
+        yc = y.astype(complex)
+        step = h * max(1.0, abs(y[j]))
+        yc[j] += 1j * step
+        J[:, j] = rhs(mech, yc, p, fixed_T).imag / step
+    return J
