@@ -1,0 +1,139 @@
+/*
+ * chem.h -- C ABI of the MI355X per-cell stiff chemistry library (libchem).
+ *
+ * The library advances, in every cell of a batch, the chemical state
+ * phi = (Y_1..Y_S, T) of a constant-pressure adiabatic homogeneous reactor
+ * over one flow step dt with an implicit BDF integrator whose Newton
+ * iteration uses the analytic chemical Jacobian.  This is the per-cell
+ * problem stated in the paper's Sec. 3.1 (at every time step and in every
+ * cell, the production rates of the state are evaluated and the state is
+ * advanced implicitly with Newton's method and the Jacobian of Eq. 7); the
+ * kinetics are Eq. 1-3 (mechanism, rates of progress, net production rates).
+ *
+ * Conventions for every call:
+ *   - Units are SI at this interface: K, Pa, s, mass fractions, and
+ *     mol/(m^3 s) for production rates.  (Rate parameters in the mechanism
+ *     text are in mol-cm-s units with Ea in kcal/mol.)
+ *   - Cell arrays are FP64, device memory (hipMalloc'd or torch CUDA
+ *     tensors), 8-byte aligned, structure-of-arrays:
+ *         T[i],  Y[k * n_cells + i]  (species-major, contiguous along cells)
+ *   - Array arguments are owned by the caller and are not retained after the
+ *     call returns.  The mechanism handle is owned by the library from
+ *     chem_mech_load* until chem_mech_free.
+ *   - A handle may be used by one host thread at a time.  Work is enqueued on
+ *     the handle's stream (chem_set_stream; default: the null stream) and
+ *     every call below returns only after that work has completed.
+ *   - Return codes: 0 = CHEM_OK, > 0 warnings, < 0 errors.  On an error the
+ *     outputs are unspecified and chem_last_error() describes the cause.
+ *     No C++ exception crosses this interface.
+ */
+#ifndef CHEM_H
+#define CHEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CHEM_OK 0
+#define CHEM_WARN_CELLS_FAILED 1  /* some cells failed; see stats and cell_status */
+#define CHEM_ERR_ARG (-1)         /* null pointer, n < 0, dt <= 0, rtol <= 0, atol < 0, p <= 0, bad option */
+#define CHEM_ERR_PARSE (-2)       /* malformed or unbalanced mechanism text */
+#define CHEM_ERR_DEVICE (-3)      /* HIP runtime error (message kept) */
+#define CHEM_ERR_OOM (-4)         /* device allocation failed */
+#define CHEM_ERR_UNSUPPORTED (-5) /* mechanism outside the supported sizes (S+1 > 64) */
+
+/* Per-cell status codes (chem_integrate_ex cell_status). */
+#define CHEM_CELL_OK 0
+#define CHEM_CELL_MAX_STEPS 1     /* step attempts exhausted; state left at the last accepted time */
+#define CHEM_CELL_H_UNDERFLOW 2   /* step size could not make progress; state at last accepted time */
+#define CHEM_CELL_BAD_INPUT 3     /* non-finite or non-positive T, or non-finite Y; cell untouched */
+
+typedef struct chem_mech chem_mech; /* opaque */
+
+/* Totals over the cells of one chem_integrate call; filled by the library. */
+typedef struct {
+  int64_t n_cells;
+  int64_t n_steps_total;     /* accepted steps, summed over cells */
+  int64_t n_steps_max;       /* largest accepted-step count of any cell */
+  int64_t n_attempts;        /* step attempts (accepted + rejected) */
+  int64_t n_rhs;             /* right-hand-side evaluations */
+  int64_t n_jac;             /* Jacobian evaluations (one per attempt) */
+  int64_t n_lu;              /* Newton-matrix factorisations */
+  int64_t n_newton_iters;
+  int64_t n_err_test_fails;
+  int64_t n_newton_fails;
+  int64_t n_cells_failed;
+  int64_t n_ir_sweeps;       /* refinement sweeps of the FP32-LU option */
+  double wall_ms;            /* device time of the integration kernels */
+} chem_stats;
+
+/* Option keys for chem_set_option (values are passed as double). */
+#define CHEM_OPT_MAX_STEPS 1    /* step attempts per cell, default 100000 */
+#define CHEM_OPT_Q_MAX 2        /* highest BDF order 1..5, default 5 */
+#define CHEM_OPT_FIXED_T 3      /* 1: hold T constant (dT/dt = 0, no enthalpy projection); default 0 */
+#define CHEM_OPT_FIXED_STEP 4   /* n > 0: n equal steps, no error test (convergence studies); default 0 */
+#define CHEM_OPT_LU_FP32 5      /* 1: factorise the Newton matrix in FP32 with FP64 residual refinement */
+#define CHEM_OPT_IR_MAX 6       /* refinement sweeps per solve for CHEM_OPT_LU_FP32, default 3 */
+
+/* Parse a mechanism from a file path / from text (format "chem-mech 1":
+ * elements with masses; species with atom counts, inert flag and linear
+ * heat capacity cp/R = a0 + a1 T plus formation enthalpy and entropy at
+ * 298.15 K; reactions of Eq. 1 with Arrhenius parameters, optional third
+ * body (unit efficiencies) or Lindemann falloff).  Validates exact atom
+ * balance of every reaction and uploads the tables to the current device.
+ * On success *out receives a new handle.  Errors: CHEM_ERR_ARG (null
+ * pointers, unreadable file), CHEM_ERR_PARSE, CHEM_ERR_UNSUPPORTED,
+ * CHEM_ERR_DEVICE, CHEM_ERR_OOM. */
+int chem_mech_load(const char* path, chem_mech** out);
+int chem_mech_load_str(const char* text, chem_mech** out);
+
+/* Release the handle and its device tables (NULL is ignored). */
+void chem_mech_free(chem_mech* m);
+
+/* Sizes of a loaded mechanism: species S, reactions R, elements E. */
+int chem_mech_info(const chem_mech* m, int* n_species, int* n_reactions, int* n_elements);
+
+/* Stream for subsequent calls (a hipStream_t, e.g. torch's
+ * current_stream().cuda_stream); NULL selects the null stream. */
+int chem_set_stream(chem_mech* m, void* hip_stream);
+
+/* Set one option (keys above).  Errors: CHEM_ERR_ARG for an unknown key or
+ * a value out of range. */
+int chem_set_option(chem_mech* m, int key, double value);
+
+/* Integrate n_cells reactors in place over [0, dt] at pressure p.
+ * T[n_cells] and Y[S * n_cells] (device, SoA) are read and overwritten with
+ * the state at dt.  rtol > 0, atol >= 0 set the WRMS error weights
+ * 1/(rtol |y| + atol) used for every component, T included.  stats (host
+ * pointer, may be NULL) receives the totals.  Returns CHEM_OK,
+ * CHEM_WARN_CELLS_FAILED if any cell failed (see the CHEM_CELL_* codes), or
+ * an error code.  n_cells == 0 is a no-op returning CHEM_OK. */
+int chem_integrate(chem_mech* m, int64_t n_cells, double* T, double* Y, double p, double dt,
+                   double rtol, double atol, chem_stats* stats);
+
+/* As chem_integrate, and additionally writes, when the pointer is not NULL,
+ * per-cell records (device memory, int32 SoA of 8 rows x n_cells):
+ * row 0 status (CHEM_CELL_*), 1 accepted steps, 2 attempts, 3 rhs
+ * evaluations, 4 Jacobian evaluations, 5 Newton iterations, 6 error-test
+ * failures, 7 Newton failures. */
+int chem_integrate_ex(chem_mech* m, int64_t n_cells, double* T, double* Y, double p, double dt,
+                      double rtol, double atol, chem_stats* stats, int32_t* cell_records);
+
+/* Rates of one state per cell (Eq. 2-3, Eq. 7): wdot[S * n] (mol m^-3 s^-1,
+ * required), f[(S+1) * n] (optional, the ODE right-hand side dY/dt, dT/dt)
+ * and jac[(S+1)^2 * n] (optional, J[i][j] = d f_i / d y_j stored at
+ * (i*(S+1)+j) * n + cell).  T, Y as in chem_integrate; p in Pa.  The
+ * CHEM_OPT_FIXED_T option applies to f and jac. */
+int chem_rates(chem_mech* m, int64_t n_cells, const double* T, const double* Y, double p, double* wdot,
+               double* f, double* jac);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char* chem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHEM_H */

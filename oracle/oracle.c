@@ -543,7 +543,8 @@ static void orc_rescale(int n, double **D, int mdim, double r) {
  * (||d - D_{k+1}||/(k+2)) give step factors 1/(1.3 e^(1/k)), 1/(1.2 e^(1/(k+1)))
  * and 1/(1.4 e^(1/(k+2))); the largest wins if it exceeds 1 (capped at 10).
  * An error test failure shrinks h by max(0.2, 0.9 e^(-1/(k+1))); three in a
- * row drop to order 1 with h /= 10.  Every change of h rescales the
+ * row drop to order 1 with h /= 10.  When t + 1.1 h reaches dt the step is set
+ * to end exactly at dt.  Every change of h rescales the
  * differences D_1..D_{min(k+1,q_max)}.  After every accepted step T is reset
  * so that the mixture enthalpy equals its initial value (adiabatic, constant
  * pressure). */
@@ -589,7 +590,9 @@ static void orc_integrate_cell(const orc_mech *m, double *y, double p, double dt
     int last = 0;
     if (fixed) {
       last = (st->steps + 1 == o->fixed_step_n);
-    } else if (t + h >= dt) {
+    } else if (t + 1.1 * h >= dt) {
+      /* end exactly at dt: stretch the step by up to 10% or shorten it, so
+       * that no sliver below the resolution of t is left over */
       double hn = dt - t;
       orc_rescale(N, D, k + 1 <= q_max ? k + 1 : q_max, hn / h);
       h = hn;

@@ -1,0 +1,179 @@
+"""Python binding of libchem (ctypes; argument marshalling only).
+
+Every step of the integration runs in the HIP kernels of libchem.so; this
+module only turns torch CUDA tensors into device pointers and the current
+stream into a hipStream_t.  Importing it does not load the library; the first
+Mechanism() does, and raises if the built library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libchem.so")
+
+CHEM_OK = 0
+CHEM_WARN_CELLS_FAILED = 1
+CHEM_ERR_ARG = -1
+CHEM_ERR_PARSE = -2
+CHEM_ERR_DEVICE = -3
+CHEM_ERR_OOM = -4
+CHEM_ERR_UNSUPPORTED = -5
+
+OPT_MAX_STEPS = 1
+OPT_Q_MAX = 2
+OPT_FIXED_T = 3
+OPT_FIXED_STEP = 4
+OPT_LU_FP32 = 5
+OPT_IR_MAX = 6
+
+EXPORTED = ("chem_mech_load", "chem_mech_load_str", "chem_mech_free", "chem_mech_info", "chem_set_stream",
+            "chem_set_option", "chem_integrate", "chem_integrate_ex", "chem_rates", "chem_last_error")
+
+
+class ChemStats(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("n_steps_total", C.c_int64), ("n_steps_max", C.c_int64),
+                ("n_attempts", C.c_int64), ("n_rhs", C.c_int64), ("n_jac", C.c_int64), ("n_lu", C.c_int64),
+                ("n_newton_iters", C.c_int64), ("n_err_test_fails", C.c_int64), ("n_newton_fails", C.c_int64),
+                ("n_cells_failed", C.c_int64), ("n_ir_sweeps", C.c_int64), ("wall_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ChemError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libchem error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: Optional[str] = None):
+    """Load libchem.so with typed signatures (raises if it is not built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libchem.so not built at {p}; run __graft_entry__.build() "
+                           "(python -m paper_2405_05974_amd.build)")
+    # torch ships its own HIP runtime under the same soname as the system one;
+    # loading torch first makes libchem bind to that copy, so the process has
+    # one runtime and device pointers/streams from torch are valid here.
+    import torch  # noqa: F401
+    lib = C.CDLL(p)
+    vp, dp, i64, i32p = C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p
+    lib.chem_mech_load.argtypes = [C.c_char_p, C.POINTER(C.c_void_p)]
+    lib.chem_mech_load_str.argtypes = [C.c_char_p, C.POINTER(C.c_void_p)]
+    lib.chem_mech_free.argtypes = [vp]
+    lib.chem_mech_free.restype = None
+    lib.chem_mech_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    lib.chem_set_stream.argtypes = [vp, vp]
+    lib.chem_set_option.argtypes = [vp, C.c_int, C.c_double]
+    lib.chem_integrate.argtypes = [vp, i64, dp, dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                   C.POINTER(ChemStats)]
+    lib.chem_integrate_ex.argtypes = [vp, i64, dp, dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                      C.POINTER(ChemStats), i32p]
+    lib.chem_rates.argtypes = [vp, i64, dp, dp, C.c_double, dp, dp, dp]
+    lib.chem_last_error.restype = C.c_char_p
+    for name in EXPORTED:
+        if name not in ("chem_mech_free", "chem_last_error"):
+            getattr(lib, name).restype = C.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(lib, rc: int) -> int:
+    if rc < 0:
+        raise ChemError(rc, lib.chem_last_error().decode())
+    return rc
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    return t.data_ptr()
+
+
+def _ptr_i32(t) -> int:
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous():
+        raise TypeError("expected a contiguous int32 CUDA tensor")
+    return t.data_ptr()
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Mechanism:
+    """A mechanism loaded into libchem (tables resident on the current device)."""
+
+    def __init__(self, text: Optional[str] = None, path: Optional[str] = None):
+        self.lib = load_library()
+        h = C.c_void_p()
+        if path is not None:
+            rc = self.lib.chem_mech_load(path.encode(), C.byref(h))
+        else:
+            rc = self.lib.chem_mech_load_str(text.encode(), C.byref(h))
+        _check(self.lib, rc)
+        self.h = h
+        S, R, E = C.c_int(), C.c_int(), C.c_int()
+        _check(self.lib, self.lib.chem_mech_info(h, C.byref(S), C.byref(R), C.byref(E)))
+        self.S, self.R, self.E = S.value, R.value, E.value
+        self.N = self.S + 1
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.chem_mech_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, key: int, value: float):
+        _check(self.lib, self.lib.chem_set_option(self.h, int(key), float(value)))
+
+    def set_options(self, max_steps=None, q_max=None, fixed_T=None, fixed_step_n=None, lu_fp32=None, ir_max=None):
+        for key, val in ((OPT_MAX_STEPS, max_steps), (OPT_Q_MAX, q_max), (OPT_FIXED_T, fixed_T),
+                         (OPT_FIXED_STEP, fixed_step_n), (OPT_LU_FP32, lu_fp32), (OPT_IR_MAX, ir_max)):
+            if val is not None:
+                self.set_option(key, float(val))
+
+    def integrate(self, T, Y, p: float, dt: float, rtol: float, atol: float, records=None, stream=None) -> dict:
+        """Advance every cell in place.  T: [n] and Y: [S, n] float64 CUDA
+        tensors; records: optional int32 CUDA tensor [8, n] for per-cell
+        records.  Returns the stats dict (plus 'rc')."""
+        n = T.numel()
+        if Y.numel() != self.S * n:
+            raise ValueError("Y must hold S * n values")
+        _check(self.lib, self.lib.chem_set_stream(self.h, _stream_handle(stream)))
+        st = ChemStats()
+        rc = self.lib.chem_integrate_ex(self.h, n, _ptr(T), _ptr(Y), float(p), float(dt), float(rtol),
+                                        float(atol), C.byref(st), _ptr_i32(records))
+        _check(self.lib, rc)
+        out = st.as_dict()
+        out["rc"] = rc
+        return out
+
+    def rates(self, T, Y, p: float, wdot, f=None, jac=None, stream=None):
+        """Production rates (mol/m^3/s), optionally the ODE rhs and Jacobian."""
+        n = T.numel()
+        _check(self.lib, self.lib.chem_set_stream(self.h, _stream_handle(stream)))
+        _check(self.lib, self.lib.chem_rates(self.h, n, _ptr(T), _ptr(Y), float(p), _ptr(wdot), _ptr(f),
+                                             _ptr(jac)))

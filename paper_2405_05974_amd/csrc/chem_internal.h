@@ -1,0 +1,65 @@
+// chem_internal.h -- device tables and launch interface shared by the host
+// library (chem_host.cpp) and the gfx950 kernels (chem_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace chemgpu {
+
+constexpr int kMaxSide = 3;              // species per reaction side
+constexpr int kSlots = 2 * kMaxSide;     // reactant slots 0..2, product slots 3..5
+constexpr int kQMax = 5;                 // highest BDF order
+constexpr int kRecRows = 8;              // per-cell record rows (see chem.h)
+constexpr int kStatCount = 12;           // device stats counters
+
+// Physical constants (CODATA 2018 gas constant, thermochemical calorie).
+constexpr double kRu = 8.31446261815324;       // J/(mol K)
+constexpr double kRuCgs = 8.31446261815324e7;  // erg/(mol K)
+constexpr double kPatm = 101325.0;             // Pa, standard-state pressure of K_c
+constexpr double kTref = 298.15;               // K, reference of the species thermo
+
+// One reaction of Eq. 1 with its rate-constant parameters (Eq. 2's k vector):
+// ln A, temperature exponent and activation temperature Ea/R, plus the
+// low-pressure limit of a Lindemann falloff.  sp[] holds the species of the
+// reactant slots 0..nr-1 and product slots 3..3+np-1 (-1 when unused).
+struct alignas(16) RxParams {
+  double lnA, b, EaR;
+  double lnA0, b0, EaR0;
+  int type;      // 0 elementary, 1 third body (+M, unit efficiencies), 2 Lindemann falloff
+  int rev;       // 1 reversible (reverse rate from K_c), 0 irreversible
+  int nr, np;
+  int sp[kSlots];
+};
+
+// Device-resident mechanism tables (all pointers are device memory).
+struct DevMech {
+  int S, R, N;       // species, reactions, N = S + 1 unknowns per cell
+  int nch;           // reaction chunks of NP reactions for the group layout
+  int np_width;      // lanes per cell (16, 32 or 64)
+  const double* W;   // [S] molecular weight g/mol
+  const double* a0;  // [S] cp/R = a0 + a1 T
+  const double* a1;
+  const double* hf;  // [S] formation enthalpy at 298.15 K, J/mol
+  const double* s0;  // [S] entropy at 298.15 K, J/(mol K)
+  const RxParams* rx;      // [R]
+  const int* csr_off;      // [S * (nch + 1)] start of species k's entries in chunk c
+  const int* csr_ent;      // entries (j << 3) | (nu_kj + 4), sorted by j per species
+};
+
+struct IntParams {
+  double p, dt, rtol, atol;
+  int max_steps, q_max, fixed_T, fixed_step_n;
+  int lu_fp32, ir_max;
+};
+
+// Launchers (chem_kernels.hip).  All enqueue on `stream` and return the HIP
+// status of the launch.
+hipError_t launch_integrate(const DevMech& m, const IntParams& prm, double* T, double* Y, int64_t n,
+                            int32_t* rec, hipStream_t stream);
+hipError_t launch_rates(const DevMech& m, double p, int fixed_T, const double* T, const double* Y, int64_t n,
+                        double* wdot, double* f, double* jac, hipStream_t stream);
+hipError_t launch_reduce_records(const int32_t* rec, int64_t n, unsigned long long* out, hipStream_t stream);
+size_t integrate_lds_bytes(int np_width, int N);
+
+}  // namespace chemgpu

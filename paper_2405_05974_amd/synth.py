@@ -318,3 +318,42 @@ def config_mechanism(cfg: int) -> Mechanism:
 
 def config_seed(cfg: int) -> int:
     return 1000 + cfg
+
+
+def load_composition_file(path: str) -> np.ndarray:
+    """Read a composition written one value per line ('#' comments)."""
+    vals = []
+    with open(path) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                vals.append(float(line))
+    return np.asarray(vals)
+
+
+def config_workload(cfg: int, yeq_dir: Optional[str] = None, shape: Optional[Tuple[int, int, int]] = None,
+                    n: Optional[int] = None) -> Workload:
+    """The named workloads (cell counts can be reduced with `shape`/`n`):
+
+    1: G(10,25,3,s0), 4096 cells, T ~ U[1000,1600], Dirichlet(1) + 0.7 inert,
+       dt 1e-5 s, rtol 1e-8, atol 1e-12
+    2: G(10,25,3,s1) planar flame in a 64x64x256 box (x = the 256 axis),
+       dt 2e-6 s, rtol 1e-8, atol 1e-12
+    3: G(53,325,4,s2) planar flame in a 16x64x256 box, dt 1e-6 s, rtol 1e-6,
+       atol 1e-12
+    """
+    m = config_mechanism(cfg)
+    seed = config_seed(cfg)
+    if cfg == 1:
+        return uniform_batch(m, n or 4096, seed, 1000.0, 1600.0, 1e-5, 1e-8, 1e-12, name="config1")
+    if cfg in (2, 3):
+        if yeq_dir is None:
+            raise ValueError("flame workloads need the directory of the equilibrium composition files")
+        S, R, E, s = CONFIG_MECH[cfg]
+        Yeq = load_composition_file(f"{yeq_dir}/yeq_G{S}_{R}_{E}_s{s}.txt")
+        if cfg == 2:
+            shape = shape or (256, 64, 64)
+            return flame_profile(m, shape, seed, Yeq, 2e-6, 1e-8, 1e-12, name="config2")
+        shape = shape or (256, 64, 16)
+        return flame_profile(m, shape, seed, Yeq, 1e-6, 1e-6, 1e-12, name="config3")
+    raise ValueError(f"no batch workload for config {cfg}")

@@ -1,0 +1,260 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.
+
+Bars: |dY| <= 1e-8 absolute and |dT|/T <= 1e-8 for the FP64 integration;
+rates, right-hand side and Jacobian to rounding-level relative tolerances.
+Each test prints its case before touching the GPU.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2405_05974_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+TOL_Y = 1e-8
+TOL_T = 1e-8
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def chem():
+    from paper_2405_05974_amd import chem as c
+    c.load_library()          # fails loudly when the HIP library is not built
+    return c
+
+
+def gpu_integrate(chem, torch_dev, mech_text, T, Y, p, dt, rtol, atol, **opts):
+    torch, dev = torch_dev
+    gm = chem.Mechanism(mech_text)
+    gm.set_options(**opts)
+    Tt = torch.tensor(np.asarray(T, dtype=np.float64), device=dev)
+    Yt = torch.tensor(np.ascontiguousarray(Y, dtype=np.float64), device=dev)
+    n = Tt.numel()
+    rec = torch.zeros((8, max(n, 1)), dtype=torch.int32, device=dev)[:, :n].contiguous() if n else None
+    st = gm.integrate(Tt, Yt, p, dt, rtol, atol, records=rec)
+    torch.cuda.synchronize()
+    recs = rec.cpu().numpy() if n else np.zeros((8, 0), np.int32)
+    return Tt.cpu().numpy(), Yt.cpu().numpy(), st, recs
+
+
+def oracle_integrate(mech_text, T, Y, p, dt, rtol, atol, **opts):
+    import oracle
+    om = oracle.Mech(mech_text)
+    return om.integrate(T, Y, p, dt, rtol, atol, **opts)
+
+
+def assert_parity(Tg, Yg, To, Yo, what):
+    dY = np.abs(Yg - Yo).max() if Yg.size else 0.0
+    dT = (np.abs(Tg - To) / np.abs(To)).max() if Tg.size else 0.0
+    say(f"{what}: max|dY|={dY:.3e} max|dT|/T={dT:.3e}")
+    assert dY <= TOL_Y, what
+    assert dT <= TOL_T, what
+
+
+# ------------------------------------------------------------------- rates
+
+@pytest.mark.parametrize("cfg", [1, 4, 3])
+def test_rates_rhs_jacobian_parity(chem, torch_dev, cfg):
+    import oracle
+    torch, dev = torch_dev
+    m = synth.config_mechanism(cfg)
+    text = m.to_text()
+    om = oracle.Mech(text)
+    n = 131                      # several groups per wave and a ragged tail
+    rng = np.random.default_rng(cfg)
+    T = rng.uniform(300.0, 3000.0, n)
+    Y = synth.composition(rng, m.n_species, 0.5, n)
+    say(f"rates cfg{cfg} n={n}")
+    gm = chem.Mechanism(text)
+    S, N = m.n_species, m.n_species + 1
+    Tt = torch.tensor(T, device=dev)
+    Yt = torch.tensor(Y, device=dev)
+    wd = torch.zeros((S, n), dtype=torch.float64, device=dev)
+    f = torch.zeros((N, n), dtype=torch.float64, device=dev)
+    J = torch.zeros((N * N, n), dtype=torch.float64, device=dev)
+    gm.rates(Tt, Yt, synth.P_ATM, wd, f, J)
+    torch.cuda.synchronize()
+    wd, f, J = wd.cpu().numpy(), f.cpu().numpy(), J.cpu().numpy()
+    nu = om.nu().astype(float)
+    worst = {"wdot": 0.0, "f": 0.0, "J": 0.0}
+    for i in range(n):
+        kf, kr, Q, wo = om.rates(T[i], Y[:, i], synth.P_ATM)
+        scale = np.abs(nu) @ np.abs(Q) + 1e-300            # sum of |terms| per species
+        e = np.abs(wd[:, i] * 1e-6 - wo) / scale
+        worst["wdot"] = max(worst["wdot"], e.max())
+        y = np.concatenate([Y[:, i], [T[i]]])
+        fo = om.rhs(y, synth.P_ATM)
+        W = om.weights()
+        rho = synth.P_ATM * 10 / (8.31446261815324e7 * T[i]) / np.sum(Y[:, i] / W)
+        H, _, Cp, _ = om.thermo(T[i])
+        den = np.sum(rho * Y[:, i] / W * Cp)
+        fscale = np.concatenate([W * scale / rho, [np.abs(H) @ scale / den]])
+        ef = np.abs(f[:, i] - fo) / fscale
+        worst["f"] = max(worst["f"], ef.max())
+        Jo = om.jac(y, synth.P_ATM)
+        Jg = J[:, i].reshape(N, N)
+        rs = np.abs(Jo).max(axis=1, keepdims=True) + 1e-300
+        worst["J"] = max(worst["J"], (np.abs(Jg - Jo) / rs).max())
+    say(f"rates cfg{cfg} worst relative: {worst}")
+    assert worst["wdot"] <= 1e-12
+    assert worst["f"] <= 1e-10
+    assert worst["J"] <= 1e-9
+
+
+# -------------------------------------------------------------- integration
+
+def test_config1_full_parity(chem, torch_dev):
+    w = synth.config_workload(1)
+    text = w.mech.to_text()
+    say(f"config1 n={w.n_cells}")
+    Tg, Yg, st, rec = gpu_integrate(chem, torch_dev, text, w.T, w.Y, w.p, w.dt, w.rtol, w.atol)
+    To, Yo, so = oracle_integrate(text, w.T, w.Y, w.p, w.dt, w.rtol, w.atol)
+    assert st["rc"] == 0 and (rec[0] == 0).all()
+    assert_parity(Tg, Yg, To, Yo, "config1")
+    same_steps = (rec[1] == so["steps"]).mean()
+    say(f"config1 identical step counts: {same_steps:.4f}; gpu steps {st['n_steps_total']} oracle {so['steps'].sum()}")
+    assert same_steps >= 0.99
+    assert st["n_steps_total"] == rec[1].sum() and st["n_steps_max"] == rec[1].max()
+    assert np.abs(Yg.sum(axis=0) - 1).max() <= 1e-10
+
+
+@pytest.mark.parametrize("n", [0, 1, 3, 5, 17])
+def test_ragged_sizes(chem, torch_dev, n):
+    w = synth.config_workload(1, n=max(n, 1))
+    T, Y = w.T[:n], w.Y[:, :n]
+    text = w.mech.to_text()
+    say(f"ragged n={n}")
+    Tg, Yg, st, rec = gpu_integrate(chem, torch_dev, text, T, Y, w.p, 1e-6, w.rtol, w.atol)
+    assert st["rc"] == 0
+    if n:
+        To, Yo, so = oracle_integrate(text, T, Y, w.p, 1e-6, w.rtol, w.atol)
+        assert_parity(Tg, Yg, To, Yo, f"ragged n={n}")
+        assert (rec[1] == so["steps"]).all()
+
+
+def test_bad_cells_and_max_steps(chem, torch_dev):
+    w = synth.config_workload(1, n=8)
+    T, Y = w.T.copy(), w.Y.copy()
+    T[1] = np.nan
+    T[2] = -5.0
+    Y[3, 5] = np.inf
+    text = w.mech.to_text()
+    say("bad cells + max_steps=3")
+    Tg, Yg, st, rec = gpu_integrate(chem, torch_dev, text, T, Y, w.p, w.dt, w.rtol, w.atol, max_steps=3)
+    To, Yo, so = oracle_integrate(text, T, Y, w.p, w.dt, w.rtol, w.atol, max_steps=3)
+    assert st["rc"] == 1 and st["n_cells_failed"] == 8
+    assert list(rec[0]) == list(so["status"])
+    assert rec[0][1] == 3 and rec[0][2] == 3 and rec[0][5] == 3 and rec[0][0] == 1
+    assert np.isnan(Tg[1]) and Tg[2] == -5.0 and np.isinf(Yg[3, 5])
+    ok = [0, 3, 4, 6, 7]
+    assert_parity(Tg[ok], Yg[:, ok], To[ok], Yo[:, ok], "max_steps=3 partial state")
+
+
+@pytest.mark.parametrize("q_max", [1, 2, 3])
+def test_lower_order_parity(chem, torch_dev, q_max):
+    w = synth.config_workload(1, n=256)
+    text = w.mech.to_text()
+    say(f"q_max={q_max}")
+    Tg, Yg, st, rec = gpu_integrate(chem, torch_dev, text, w.T, w.Y, w.p, 2e-6, w.rtol, w.atol, q_max=q_max)
+    To, Yo, so = oracle_integrate(text, w.T, w.Y, w.p, 2e-6, w.rtol, w.atol, q_max=q_max)
+    assert_parity(Tg, Yg, To, Yo, f"q_max={q_max}")
+
+
+def test_fixed_T_and_fixed_step_parity(chem, torch_dev):
+    w = synth.config_workload(1, n=64)
+    text = w.mech.to_text()
+    say("fixed_T")
+    Tg, Yg, st, rec = gpu_integrate(chem, torch_dev, text, w.T, w.Y, w.p, w.dt, w.rtol, w.atol, fixed_T=1)
+    To, Yo, so = oracle_integrate(text, w.T, w.Y, w.p, w.dt, w.rtol, w.atol, fixed_T=True)
+    assert np.array_equal(Tg, w.T)
+    assert_parity(Tg, Yg, To, Yo, "fixed_T")
+    say("fixed_step n=400 q=2")
+    Tg, Yg, st, rec = gpu_integrate(chem, torch_dev, text, w.T, w.Y, w.p, 1e-9, w.rtol, w.atol, fixed_step_n=400,
+                                    q_max=2)
+    To, Yo, so = oracle_integrate(text, w.T, w.Y, w.p, 1e-9, w.rtol, w.atol, fixed_step_n=400, q_max=2)
+    assert (rec[1] == 400).all()
+    assert_parity(Tg, Yg, To, Yo, "fixed_step")
+
+
+@pytest.mark.parametrize("kind", ["elementary", "third_body", "falloff"])
+def test_gpu_closed_form_isomerisation(chem, torch_dev, kind):
+    from tests import mechs
+    T0 = 1200.0
+    conc = synth.P_ATM / (mechs.RU * T0) * 1e-6
+    if kind == "elementary":
+        m = mechs.isomer_pair(A=1e5, b=0.3, Ea=8.0)
+        k = mechs.kf_arrhenius(1e5, 0.3, 8.0, T0)
+    elif kind == "third_body":
+        m = mechs.isomer_pair(A=1e10, b=0.0, Ea=3.0, kind=1)
+        k = mechs.kf_arrhenius(1e10, 0.0, 3.0, T0) * conc
+    else:
+        m = mechs.isomer_pair(A=2e3, b=0.1, Ea=4.0, kind=2, low=(1e9, 0.0, 4.0))
+        kinf = mechs.kf_arrhenius(2e3, 0.1, 4.0, T0)
+        Pr = mechs.kf_arrhenius(1e9, 0.0, 4.0, T0) * conc / kinf
+        k = kinf * Pr / (1 + Pr)
+    dt = 2.5 / k
+    Y0 = np.array([[0.25] * 5, [0.05] * 5, [0.70] * 5])
+    say(f"closed form {kind}")
+    Tg, Yg, st, rec = gpu_integrate(chem, torch_dev, m.to_text(), np.full(5, T0), Y0, synth.P_ATM, dt, 1e-12, 1e-20)
+    assert np.abs(Tg - T0).max() <= 1e-10 * T0
+    assert np.abs(Yg[0] / (0.25 * np.exp(-2.5)) - 1).max() <= 1e-8
+
+
+def test_determinism(chem, torch_dev):
+    w = synth.config_workload(1, n=512)
+    text = w.mech.to_text()
+    say("determinism")
+    a = gpu_integrate(chem, torch_dev, text, w.T, w.Y, w.p, w.dt, w.rtol, w.atol)
+    b = gpu_integrate(chem, torch_dev, text, w.T, w.Y, w.p, w.dt, w.rtol, w.atol)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[3], b[3])
+
+
+def test_config4_mechanism_sample(chem, torch_dev):
+    m = synth.config_mechanism(4)
+    boxes = synth.amr_boxes(m, 6, synth.config_seed(4), max_cells=24)
+    text = m.to_text()
+    for bi, bx in enumerate(boxes):
+        say(f"config4 box {bi} n={bx.T.size} dt={bx.dt:.3e}")
+        Tg, Yg, st, rec = gpu_integrate(chem, torch_dev, text, bx.T, bx.Y, synth.P_ATM, bx.dt, 1e-8, 1e-12)
+        To, Yo, so = oracle_integrate(text, bx.T, bx.Y, synth.P_ATM, bx.dt, 1e-8, 1e-12)
+        assert_parity(Tg, Yg, To, Yo, f"config4 box {bi}")
+
+
+def test_config3_sample(chem, torch_dev):
+    w = synth.config_workload(3, GOLDEN, shape=(256, 1, 1))
+    idx = np.arange(0, 256, 8)
+    text = w.mech.to_text()
+    say(f"config3 sample n={idx.size}")
+    Tg, Yg, st, rec = gpu_integrate(chem, torch_dev, text, w.T[idx], w.Y[:, idx], w.p, w.dt, w.rtol, w.atol)
+    To, Yo, so = oracle_integrate(text, w.T[idx], w.Y[:, idx], w.p, w.dt, w.rtol, w.atol)
+    assert_parity(Tg, Yg, To, Yo, "config3 sample")
+
+
+def test_config2_full_box_sampled(chem, torch_dev):
+    """The benchmark workload at full size (1,048,576 cells): oracle on a
+    strided sample spanning the flame, invariants on every cell."""
+    w = synth.config_workload(2, GOLDEN)
+    text = w.mech.to_text()
+    say(f"config2 full n={w.n_cells}")
+    Tg, Yg, st, rec = gpu_integrate(chem, torch_dev, text, w.T, w.Y, w.p, w.dt, w.rtol, w.atol)
+    assert st["rc"] == 0 and st["n_cells_failed"] == 0
+    idx = np.arange(0, w.n_cells, 4096 // 2 + 7)
+    To, Yo, so = oracle_integrate(text, w.T[idx], w.Y[:, idx], w.p, w.dt, w.rtol, w.atol)
+    assert_parity(Tg[idx], Yg[:, idx], To, Yo, "config2 sample")
+    assert np.abs(Yg.sum(axis=0) - 1).max() <= 1e-9
+    assert np.isfinite(Tg).all() and (Tg > 0).all()
