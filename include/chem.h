@@ -76,6 +76,9 @@ typedef struct {
 #define CHEM_OPT_FIXED_STEP 4   /* n > 0: n equal steps, no error test (convergence studies); default 0 */
 #define CHEM_OPT_LU_FP32 5      /* 1: factorise the Newton matrix in FP32 with FP64 residual refinement */
 #define CHEM_OPT_IR_MAX 6       /* refinement sweeps per solve for CHEM_OPT_LU_FP32, default 3 */
+#define CHEM_OPT_GRAPH 7        /* 1: chem_integrate_boxes replays a captured hipGraph (default 1) */
+#define CHEM_OPT_WAVES_PER_CU 8 /* resident waves per CU for chem_integrate_boxes' persistent grid (1..32) */
+#define CHEM_OPT_GROUP_WIDTH 9  /* lanes per cell: 16, 32 or 64, at least S+1 (default: the smallest) */
 
 /* Parse a mechanism from a file path / from text (format "chem-mech 1":
  * elements with masses; species with atom counts, inert flag and linear
@@ -114,12 +117,32 @@ int chem_integrate(chem_mech* m, int64_t n_cells, double* T, double* Y, double p
                    double rtol, double atol, chem_stats* stats);
 
 /* As chem_integrate, and additionally writes, when the pointer is not NULL,
- * per-cell records (device memory, int32 SoA of 8 rows x n_cells):
+ * per-cell records (device memory, int32 SoA of 9 rows x n_cells):
  * row 0 status (CHEM_CELL_*), 1 accepted steps, 2 attempts, 3 rhs
  * evaluations, 4 Jacobian evaluations, 5 Newton iterations, 6 error-test
- * failures, 7 Newton failures. */
+ * failures, 7 Newton failures, 8 refinement sweeps (CHEM_OPT_LU_FP32). */
 int chem_integrate_ex(chem_mech* m, int64_t n_cells, double* T, double* Y, double p, double dt,
                       double rtol, double atol, chem_stats* stats, int32_t* cell_records);
+
+/* One box of cells for chem_integrate_boxes (device SoA arrays of that box). */
+typedef struct {
+  double* T;        /* [n_cells] */
+  double* Y;        /* [S * n_cells], Y[k * n_cells + i] */
+  int64_t n_cells;
+  double dt;        /* flow step of this box, s (> 0) */
+} chem_box;
+
+/* Integrate many boxes of uneven size, each over its own dt, in one
+ * persistent launch: the paper's AMR setting, where every box of every level
+ * advances its chemistry over the flow step (Sec. 5).  Work items are tiles
+ * of one wave's cells taken from a device queue, largest boxes first; all
+ * options of chem_integrate apply.  boxes is a host array; the T/Y arrays are
+ * device memory, updated in place.  box_ms (host, optional, n_boxes entries)
+ * receives each box's completion time in ms from the launch, observed on the
+ * host through host-mapped flags.  stats totals cover every cell of every box.
+ * Returns as chem_integrate. */
+int chem_integrate_boxes(chem_mech* m, int n_boxes, const chem_box* boxes, double p, double rtol, double atol,
+                         chem_stats* stats, double* box_ms);
 
 /* Rates of one state per cell (Eq. 2-3, Eq. 7): wdot[S * n] (mol m^-3 s^-1,
  * required), f[(S+1) * n] (optional, the ODE right-hand side dY/dt, dT/dt)

@@ -29,8 +29,15 @@ OPT_FIXED_STEP = 4
 OPT_LU_FP32 = 5
 OPT_IR_MAX = 6
 
+RECORD_ROWS = 9   # per-cell record rows of chem_integrate_ex
+
+OPT_GRAPH = 7
+OPT_WAVES_PER_CU = 8
+OPT_GROUP_WIDTH = 9
+
 EXPORTED = ("chem_mech_load", "chem_mech_load_str", "chem_mech_free", "chem_mech_info", "chem_set_stream",
-            "chem_set_option", "chem_integrate", "chem_integrate_ex", "chem_rates", "chem_last_error")
+            "chem_set_option", "chem_integrate", "chem_integrate_ex", "chem_integrate_boxes", "chem_rates",
+            "chem_last_error")
 
 
 class ChemStats(C.Structure):
@@ -41,6 +48,10 @@ class ChemStats(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ChemBox(C.Structure):
+    _fields_ = [("T", C.c_void_p), ("Y", C.c_void_p), ("n_cells", C.c_int64), ("dt", C.c_double)]
 
 
 class ChemError(RuntimeError):
@@ -78,6 +89,8 @@ def load_library(path: Optional[str] = None):
                                    C.POINTER(ChemStats)]
     lib.chem_integrate_ex.argtypes = [vp, i64, dp, dp, C.c_double, C.c_double, C.c_double, C.c_double,
                                       C.POINTER(ChemStats), i32p]
+    lib.chem_integrate_boxes.argtypes = [vp, C.c_int, C.POINTER(ChemBox), C.c_double, C.c_double, C.c_double,
+                                         C.POINTER(ChemStats), C.POINTER(C.c_double)]
     lib.chem_rates.argtypes = [vp, i64, dp, dp, C.c_double, dp, dp, dp]
     lib.chem_last_error.restype = C.c_char_p
     for name in EXPORTED:
@@ -149,19 +162,23 @@ class Mechanism:
     def set_option(self, key: int, value: float):
         _check(self.lib, self.lib.chem_set_option(self.h, int(key), float(value)))
 
-    def set_options(self, max_steps=None, q_max=None, fixed_T=None, fixed_step_n=None, lu_fp32=None, ir_max=None):
+    def set_options(self, max_steps=None, q_max=None, fixed_T=None, fixed_step_n=None, lu_fp32=None, ir_max=None,
+                    graph=None, waves_per_cu=None, group_width=None):
         for key, val in ((OPT_MAX_STEPS, max_steps), (OPT_Q_MAX, q_max), (OPT_FIXED_T, fixed_T),
-                         (OPT_FIXED_STEP, fixed_step_n), (OPT_LU_FP32, lu_fp32), (OPT_IR_MAX, ir_max)):
+                         (OPT_FIXED_STEP, fixed_step_n), (OPT_LU_FP32, lu_fp32), (OPT_IR_MAX, ir_max),
+                         (OPT_GRAPH, graph), (OPT_WAVES_PER_CU, waves_per_cu), (OPT_GROUP_WIDTH, group_width)):
             if val is not None:
                 self.set_option(key, float(val))
 
     def integrate(self, T, Y, p: float, dt: float, rtol: float, atol: float, records=None, stream=None) -> dict:
         """Advance every cell in place.  T: [n] and Y: [S, n] float64 CUDA
-        tensors; records: optional int32 CUDA tensor [8, n] for per-cell
+        tensors; records: optional int32 CUDA tensor [9, n] for per-cell
         records.  Returns the stats dict (plus 'rc')."""
         n = T.numel()
         if Y.numel() != self.S * n:
             raise ValueError("Y must hold S * n values")
+        if records is not None and records.numel() != RECORD_ROWS * n:
+            raise ValueError(f"records must hold {RECORD_ROWS} x n int32 values")
         _check(self.lib, self.lib.chem_set_stream(self.h, _stream_handle(stream)))
         st = ChemStats()
         rc = self.lib.chem_integrate_ex(self.h, n, _ptr(T), _ptr(Y), float(p), float(dt), float(rtol),
@@ -170,6 +187,26 @@ class Mechanism:
         out = st.as_dict()
         out["rc"] = rc
         return out
+
+    def integrate_boxes(self, boxes, p: float, rtol: float, atol: float, box_ms: bool = False, stream=None):
+        """boxes: list of (T, Y, dt) with T [n_b] and Y [S, n_b] float64 CUDA
+        tensors, updated in place.  Returns (stats dict, per-box completion
+        times in ms or None)."""
+        arr = (ChemBox * max(len(boxes), 1))()
+        for i, (T, Y, dt) in enumerate(boxes):
+            n = T.numel()
+            if Y.numel() != self.S * n:
+                raise ValueError("Y must hold S * n values")
+            arr[i] = ChemBox(_ptr(T) if n else None, _ptr(Y) if n else None, n, float(dt))
+        ms = (C.c_double * max(len(boxes), 1))() if box_ms else None
+        _check(self.lib, self.lib.chem_set_stream(self.h, _stream_handle(stream)))
+        st = ChemStats()
+        rc = self.lib.chem_integrate_boxes(self.h, len(boxes), arr, float(p), float(rtol), float(atol),
+                                           C.byref(st), ms)
+        _check(self.lib, rc)
+        out = st.as_dict()
+        out["rc"] = rc
+        return out, (list(ms)[:len(boxes)] if box_ms else None)
 
     def rates(self, T, Y, p: float, wdot, f=None, jac=None, stream=None):
         """Production rates (mol/m^3/s), optionally the ODE rhs and Jacobian."""

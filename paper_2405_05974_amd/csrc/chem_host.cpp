@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -146,15 +147,32 @@ struct chem_mech {
   HostMech host;
   DevMech dev{};
   void* blob = nullptr;          // device tables
+  const int* csr_off_np[3] = {nullptr, nullptr, nullptr};   // chunk offsets for 16/32/64 lanes per cell
+  int nch_np[3] = {0, 0, 0};
   hipStream_t stream = nullptr;
   int device = 0;
+  int n_cu = 256;
   // options
   int max_steps = 100000, q_max = 5, fixed_T = 0, fixed_step_n = 0, lu_fp32 = 0, ir_max = 3;
+  int use_graph = 1, waves_per_cu = 8;
   // workspace
   int32_t* rec = nullptr;
   int64_t rec_cap = 0;
   unsigned long long* dstats = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // batched boxes
+  chemgpu::BoxDev* dboxes = nullptr;
+  int* dremaining = nullptr;
+  int box_cap = 0;
+  chemgpu::BoxJob* djob = nullptr;
+  unsigned* dhead = nullptr;
+  int* host_done = nullptr;      // pinned, mapped
+  int* host_done_dev = nullptr;
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  const void* graph_key[4] = {nullptr, nullptr, nullptr, nullptr};
+  int graph_grid = 0, graph_np = 0, graph_f32 = -1;
+  IntParams graph_prm{};           // integration parameters baked into the captured launch
 };
 
 namespace {
@@ -164,7 +182,7 @@ int upload(chem_mech* h) {
   const int S = (int)m.W.size(), R = (int)m.rx.size(), N = S + 1;
   if (N > 64) return fail(CHEM_ERR_UNSUPPORTED, "mechanisms with more than 63 species are not supported");
   const int np = N <= 16 ? 16 : (N <= 32 ? 32 : 64);
-  const int nch = std::max(1, (R + np - 1) / np);
+  const int widths[3] = {16, 32, 64};
 
   std::vector<RxParams> rx(std::max(R, 1));
   const double kcal_to_K = 4184.0 / chemgpu::kRu;   // Ea/R per kcal/mol
@@ -188,21 +206,43 @@ int upload(chem_mech* h) {
     for (int i = 0; i < d.nr; ++i) d.sp[i] = x.reac[i];
     for (int i = 0; i < d.np; ++i) d.sp[chemgpu::kMaxSide + i] = x.prod[i];
   }
-  // per-species lists of (reaction, net coefficient), reaction order, split in chunks
-  std::vector<int> off((size_t)S * (nch + 1), 0), ent;
+  // per-species lists of (reaction, net coefficient) in reaction order; for
+  // each group width the list is split in chunks of that many reactions
+  std::vector<int> ent, ent_start(S + 1, 0);
+  std::vector<int> ent_j;
   for (int k = 0; k < S; ++k) {
-    int ch_next = 0;
+    ent_start[k] = (int)ent.size();
     for (int j = 0; j < R; ++j) {
       int nu = 0;
       for (int s : m.rx[j].prod) nu += (s == k);
       for (int s : m.rx[j].reac) nu -= (s == k);
       if (nu == 0) continue;
-      while (ch_next <= j / np) off[(size_t)k * (nch + 1) + ch_next++] = (int)ent.size();
       ent.push_back((j << 3) | (nu + 4));
+      ent_j.push_back(j);
     }
-    while (ch_next <= nch) off[(size_t)k * (nch + 1) + ch_next++] = (int)ent.size();
+  }
+  ent_start[S] = (int)ent.size();
+  std::vector<int> offs[3];
+  int nchs[3] = {0, 0, 0};
+  for (int wi = 0; wi < 3; ++wi) {
+    const int w = widths[wi];
+    const int nch = std::max(1, (R + w - 1) / w);
+    nchs[wi] = nch;
+    offs[wi].assign((size_t)S * (nch + 1), 0);
+    for (int k = 0; k < S; ++k)
+      for (int c = 0; c <= nch; ++c) {
+        int e = ent_start[k];
+        while (e < ent_start[k + 1] && ent_j[e] < c * w) ++e;
+        offs[wi][(size_t)k * (nch + 1) + c] = e;
+      }
   }
   if (ent.empty()) ent.push_back(0);
+  std::vector<int> off;
+  size_t off_at[3];
+  for (int wi = 0; wi < 3; ++wi) {
+    off_at[wi] = off.size();
+    off.insert(off.end(), offs[wi].begin(), offs[wi].end());
+  }
 
   auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t o_sp = 0;
@@ -240,7 +280,6 @@ int upload(chem_mech* h) {
   dm.S = S;
   dm.R = R;
   dm.N = N;
-  dm.nch = nch;
   dm.np_width = np;
   const double* dsp = reinterpret_cast<const double*>(base + o_sp);
   dm.W = dsp;
@@ -249,8 +288,16 @@ int upload(chem_mech* h) {
   dm.hf = dsp + 3 * S;
   dm.s0 = dsp + 4 * S;
   dm.rx = reinterpret_cast<const RxParams*>(base + o_rx);
-  dm.csr_off = reinterpret_cast<const int*>(base + o_off);
+  for (int wi = 0; wi < 3; ++wi) {
+    h->csr_off_np[wi] = reinterpret_cast<const int*>(base + o_off) + off_at[wi];
+    h->nch_np[wi] = nchs[wi];
+  }
+  dm.csr_off = h->csr_off_np[np == 16 ? 0 : (np == 32 ? 1 : 2)];
+  dm.nch = h->nch_np[np == 16 ? 0 : (np == 32 ? 1 : 2)];
   dm.csr_ent = reinterpret_cast<const int*>(base + o_ent);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, h->device) == hipSuccess && prop.multiProcessorCount > 0)
+    h->n_cu = prop.multiProcessorCount;
   e = hipMalloc(&h->dstats, sizeof(unsigned long long) * chemgpu::kStatCount);
   if (e != hipSuccess) return fail(CHEM_ERR_OOM, "hipMalloc of stats");
   if ((e = hipEventCreate(&h->ev0)) != hipSuccess || (e = hipEventCreate(&h->ev1)) != hipSuccess)
@@ -272,6 +319,22 @@ int load_text(const std::string& text, chem_mech** out) {
   *out = h;
   g_last_error.clear();
   return CHEM_OK;
+}
+
+void fill_stats(chem_stats* stats, int64_t n_cells, const unsigned long long* hs, float ms) {
+  stats->n_cells = n_cells;
+  stats->n_steps_total = (int64_t)hs[0];
+  stats->n_steps_max = (int64_t)hs[1];
+  stats->n_attempts = (int64_t)hs[2];
+  stats->n_rhs = (int64_t)hs[3];
+  stats->n_jac = (int64_t)hs[4];
+  stats->n_lu = (int64_t)hs[4];
+  stats->n_newton_iters = (int64_t)hs[5];
+  stats->n_err_test_fails = (int64_t)hs[6];
+  stats->n_newton_fails = (int64_t)hs[7];
+  stats->n_cells_failed = (int64_t)hs[8];
+  stats->n_ir_sweeps = (int64_t)hs[9];
+  stats->wall_ms = ms;
 }
 
 int ensure_records(chem_mech* h, int64_t n) {
@@ -321,6 +384,13 @@ void chem_mech_free(chem_mech* m) {
   if (m->dstats) (void)hipFree(m->dstats);
   if (m->ev0) (void)hipEventDestroy(m->ev0);
   if (m->ev1) (void)hipEventDestroy(m->ev1);
+  if (m->dboxes) (void)hipFree(m->dboxes);
+  if (m->dremaining) (void)hipFree(m->dremaining);
+  if (m->djob) (void)hipFree(m->djob);
+  if (m->dhead) (void)hipFree(m->dhead);
+  if (m->host_done) (void)hipHostFree(m->host_done);
+  if (m->graph) (void)hipGraphExecDestroy(m->graph);
+  if (m->capture_stream) (void)hipStreamDestroy(m->capture_stream);
   delete m;
 }
 
@@ -365,6 +435,21 @@ int chem_set_option(chem_mech* m, int key, double value) {
       if (v < 0 || v > 20) return fail(CHEM_ERR_ARG, "ir_max must be 0..20");
       m->ir_max = (int)v;
       return CHEM_OK;
+    case CHEM_OPT_GRAPH:
+      m->use_graph = v != 0;
+      return CHEM_OK;
+    case CHEM_OPT_WAVES_PER_CU:
+      if (v < 1 || v > 32) return fail(CHEM_ERR_ARG, "waves_per_cu must be 1..32");
+      m->waves_per_cu = (int)v;
+      return CHEM_OK;
+    case CHEM_OPT_GROUP_WIDTH: {
+      const int wi = v == 16 ? 0 : (v == 32 ? 1 : (v == 64 ? 2 : -1));
+      if (wi < 0 || v < m->dev.N) return fail(CHEM_ERR_ARG, "group width must be 16, 32 or 64 and at least S+1");
+      m->dev.np_width = (int)v;
+      m->dev.csr_off = m->csr_off_np[wi];
+      m->dev.nch = m->nch_np[wi];
+      return CHEM_OK;
+    }
     default:
       return fail(CHEM_ERR_ARG, "unknown option key " + std::to_string(key));
   }
@@ -414,21 +499,7 @@ int chem_integrate_ex(chem_mech* m, int64_t n_cells, double* T, double* Y, doubl
   if (e != hipSuccess) return hip_fail(e, "integrate");
   float ms = 0.0f;
   (void)hipEventElapsedTime(&ms, m->ev0, m->ev1);
-  if (stats) {
-    stats->n_cells = n_cells;
-    stats->n_steps_total = (int64_t)hs[0];
-    stats->n_steps_max = (int64_t)hs[1];
-    stats->n_attempts = (int64_t)hs[2];
-    stats->n_rhs = (int64_t)hs[3];
-    stats->n_jac = (int64_t)hs[4];
-    stats->n_lu = (int64_t)hs[4];
-    stats->n_newton_iters = (int64_t)hs[5];
-    stats->n_err_test_fails = (int64_t)hs[6];
-    stats->n_newton_fails = (int64_t)hs[7];
-    stats->n_cells_failed = (int64_t)hs[8];
-    stats->n_ir_sweeps = 0;
-    stats->wall_ms = ms;
-  }
+  if (stats) fill_stats(stats, n_cells, hs, ms);
   g_last_error.clear();
   return hs[8] ? CHEM_WARN_CELLS_FAILED : CHEM_OK;
 }
@@ -436,6 +507,180 @@ int chem_integrate_ex(chem_mech* m, int64_t n_cells, double* T, double* Y, doubl
 int chem_integrate(chem_mech* m, int64_t n_cells, double* T, double* Y, double p, double dt, double rtol,
                    double atol, chem_stats* stats) {
   return chem_integrate_ex(m, n_cells, T, Y, p, dt, rtol, atol, stats, nullptr);
+}
+
+namespace {
+
+int ensure_boxes(chem_mech* m, int n_boxes) {
+  if (!m->djob) {
+    if (hipMalloc(&m->djob, sizeof(chemgpu::BoxJob)) != hipSuccess || hipMalloc(&m->dhead, sizeof(unsigned)) != hipSuccess)
+      return fail(CHEM_ERR_OOM, "hipMalloc of queue state");
+  }
+  if (!m->capture_stream && hipStreamCreateWithFlags(&m->capture_stream, hipStreamNonBlocking) != hipSuccess)
+    return fail(CHEM_ERR_DEVICE, "hipStreamCreate");
+  if (n_boxes <= m->box_cap) return CHEM_OK;
+  if (m->dboxes) (void)hipFree(m->dboxes);
+  if (m->dremaining) (void)hipFree(m->dremaining);
+  if (m->host_done) (void)hipHostFree(m->host_done);
+  m->dboxes = nullptr;
+  m->dremaining = nullptr;
+  m->host_done = nullptr;
+  m->box_cap = 0;
+  const int cap = std::max(n_boxes, 256);
+  if (hipMalloc(&m->dboxes, sizeof(chemgpu::BoxDev) * cap) != hipSuccess ||
+      hipMalloc(&m->dremaining, sizeof(int) * cap) != hipSuccess)
+    return fail(CHEM_ERR_OOM, "hipMalloc of box descriptors");
+  if (hipHostMalloc(reinterpret_cast<void**>(&m->host_done), sizeof(int) * cap, hipHostMallocMapped) != hipSuccess ||
+      hipHostGetDevicePointer(reinterpret_cast<void**>(&m->host_done_dev), m->host_done, 0) != hipSuccess)
+    return fail(CHEM_ERR_OOM, "hipHostMalloc of completion flags");
+  m->box_cap = cap;
+  return CHEM_OK;
+}
+
+// Enqueue queue reset + persistent kernel (+ stats reduction) on `s`.
+hipError_t enqueue_boxes(chem_mech* m, const IntParams& prm, int grid, hipStream_t s) {
+  hipError_t e = chemgpu::launch_boxes(m->dev, prm, m->dboxes, m->djob, m->dhead, m->dremaining, m->rec,
+                                       m->host_done_dev, grid, s);
+  if (e != hipSuccess) return e;
+  return chemgpu::launch_reduce_records_job(m->rec, m->djob, m->dstats, s);
+}
+
+}  // namespace
+
+int chem_integrate_boxes(chem_mech* m, int n_boxes, const chem_box* boxes, double p, double rtol, double atol,
+                         chem_stats* stats, double* box_ms) {
+  if (!m) return fail(CHEM_ERR_ARG, "mechanism is NULL");
+  if (n_boxes < 0 || (n_boxes > 0 && !boxes)) return fail(CHEM_ERR_ARG, "bad box array");
+  if (!(rtol > 0) || !std::isfinite(rtol)) return fail(CHEM_ERR_ARG, "rtol must be positive");
+  if (!(atol >= 0) || !std::isfinite(atol)) return fail(CHEM_ERR_ARG, "atol must be >= 0");
+  if (!(p > 0) || !std::isfinite(p)) return fail(CHEM_ERR_ARG, "p must be positive");
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  if (n_boxes == 0) return CHEM_OK;
+  for (int b = 0; b < n_boxes; ++b) {
+    if (boxes[b].n_cells < 0 || (boxes[b].n_cells > 0 && (!boxes[b].T || !boxes[b].Y)))
+      return fail(CHEM_ERR_ARG, "box " + std::to_string(b) + ": bad arrays");
+    if (!(boxes[b].dt > 0) || !std::isfinite(boxes[b].dt))
+      return fail(CHEM_ERR_ARG, "box " + std::to_string(b) + ": dt must be positive");
+  }
+  try {
+    // queue order: largest boxes first (their tiles start earliest)
+    std::vector<int> order(n_boxes);
+    for (int b = 0; b < n_boxes; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return boxes[a].n_cells > boxes[b].n_cells; });
+    const int cpw = 64 / m->dev.np_width;
+    std::vector<chemgpu::BoxDev> q(n_boxes);
+    int64_t tiles = 0, cells = 0;
+    for (int i = 0; i < n_boxes; ++i) {
+      const chem_box& bx = boxes[order[i]];
+      q[i].T = bx.T;
+      q[i].Y = bx.Y;
+      q[i].n = bx.n_cells;
+      q[i].dt = bx.dt;
+      q[i].cell_off = cells;
+      q[i].tile_pre = tiles;
+      q[i].box_id = order[i];
+      q[i].pad = 0;
+      tiles += (bx.n_cells + cpw - 1) / cpw;
+      cells += bx.n_cells;
+    }
+    if (tiles > (int64_t)0x7fffffff) return fail(CHEM_ERR_ARG, "too many cells in one call");
+    if (cells == 0) return CHEM_OK;
+    int rc = ensure_boxes(m, n_boxes);
+    if (rc != CHEM_OK) return rc;
+    const void* old_rec = m->rec;
+    rc = ensure_records(m, cells);
+    if (rc != CHEM_OK) return rc;
+    chemgpu::BoxJob job{n_boxes, (unsigned)tiles, cells};
+    hipError_t e = hipMemcpyAsync(m->dboxes, q.data(), sizeof(chemgpu::BoxDev) * n_boxes, hipMemcpyHostToDevice,
+                                  m->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(m->djob, &job, sizeof job, hipMemcpyHostToDevice, m->stream);
+    if (e != hipSuccess) return hip_fail(e, "box descriptor upload");
+    e = hipStreamSynchronize(m->stream);   // host copies above read stack memory
+    if (e != hipSuccess) return hip_fail(e, "box descriptor upload");
+    std::memset(m->host_done, 0, sizeof(int) * n_boxes);
+    IntParams prm;
+    std::memset(&prm, 0, sizeof prm);   // padding included: the struct is compared bytewise
+    prm.p = p;
+    prm.dt = 0.0;
+    prm.rtol = rtol;
+    prm.atol = atol;
+    prm.max_steps = m->max_steps;
+    prm.q_max = m->q_max;
+    prm.fixed_T = m->fixed_T;
+    prm.fixed_step_n = m->fixed_step_n;
+    prm.lu_fp32 = m->lu_fp32;
+    prm.ir_max = m->ir_max;
+    const int grid = (int)std::min<int64_t>(tiles, (int64_t)m->waves_per_cu * m->n_cu);
+    const auto t0 = std::chrono::steady_clock::now();
+    e = hipEventRecord(m->ev0, m->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if (m->use_graph) {
+      const void* key[4] = {m->rec, m->dboxes, m->host_done_dev, m->blob};
+      const bool stale = !m->graph || std::memcmp(key, m->graph_key, sizeof key) != 0 || m->graph_grid != grid ||
+                         m->graph_np != m->dev.np_width || m->graph_f32 != m->lu_fp32 || old_rec != m->rec ||
+                         std::memcmp(&prm, &m->graph_prm, sizeof prm) != 0;
+      if (stale) {
+        if (m->graph) (void)hipGraphExecDestroy(m->graph);
+        m->graph = nullptr;
+        hipGraph_t gr = nullptr;
+        e = hipStreamBeginCapture(m->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+          const hipError_t le = enqueue_boxes(m, prm, grid, m->capture_stream);
+          e = hipStreamEndCapture(m->capture_stream, &gr);
+          if (le != hipSuccess) e = le;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&m->graph, gr, nullptr, nullptr, 0);
+        if (gr) (void)hipGraphDestroy(gr);
+        if (e != hipSuccess) return hip_fail(e, "hipGraph capture of the box launch");
+        std::memcpy(m->graph_key, key, sizeof key);
+        m->graph_grid = grid;
+        m->graph_np = m->dev.np_width;
+        m->graph_f32 = m->lu_fp32;
+        m->graph_prm = prm;
+      }
+      // the captured kernels take their per-call parameters from device memory,
+      // except the integration options baked into the capture
+      e = hipGraphLaunch(m->graph, m->stream);
+    } else {
+      e = enqueue_boxes(m, prm, grid, m->stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "box launch");
+    e = hipEventRecord(m->ev1, m->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if (box_ms) {
+      std::vector<char> seen(n_boxes, 0);
+      int left = n_boxes;
+      volatile int* flags = m->host_done;
+      while (left > 0) {
+        for (int b = 0; b < n_boxes; ++b) {
+          if (!seen[b] && flags[b]) {
+            seen[b] = 1;
+            --left;
+            box_ms[b] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+          }
+        }
+        if (left > 0 && hipStreamQuery(m->stream) != hipErrorNotReady) {
+          // the stream is done (or failed): every remaining box is complete
+          const double now = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+          for (int b = 0; b < n_boxes; ++b)
+            if (!seen[b]) box_ms[b] = flags[b] ? now : -1.0;
+          left = 0;
+        }
+      }
+    }
+    unsigned long long hs[chemgpu::kStatCount];
+    e = hipMemcpyAsync(hs, m->dstats, sizeof hs, hipMemcpyDeviceToHost, m->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    if (e != hipSuccess) return hip_fail(e, "box integration");
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, m->ev0, m->ev1);
+    if (stats) fill_stats(stats, cells, hs, ms);
+    g_last_error.clear();
+    return hs[8] ? CHEM_WARN_CELLS_FAILED : CHEM_OK;
+  } catch (...) {
+    return fail(CHEM_ERR_OOM, "exception in chem_integrate_boxes");
+  }
 }
 
 int chem_rates(chem_mech* m, int64_t n_cells, const double* T, const double* Y, double p, double* wdot, double* f,

@@ -10,7 +10,7 @@ namespace chemgpu {
 constexpr int kMaxSide = 3;              // species per reaction side
 constexpr int kSlots = 2 * kMaxSide;     // reactant slots 0..2, product slots 3..5
 constexpr int kQMax = 5;                 // highest BDF order
-constexpr int kRecRows = 8;              // per-cell record rows (see chem.h)
+constexpr int kRecRows = 9;              // per-cell record rows (see chem.h)
 constexpr int kStatCount = 12;           // device stats counters
 
 // Physical constants (CODATA 2018 gas constant, thermochemical calorie).
@@ -47,6 +47,24 @@ struct DevMech {
   const int* csr_ent;      // entries (j << 3) | (nu_kj + 4), sorted by j per species
 };
 
+// One box of the batched entry point, in queue order.
+struct BoxDev {
+  double* T;           // [n] device
+  double* Y;           // [S * n] device, SoA within the box
+  int64_t n;           // cells
+  double dt;           // flow step of this box, s
+  int64_t cell_off;    // first column of this box in the record array
+  int64_t tile_pre;    // first queue item of this box
+  int box_id;          // index in the caller's box array
+  int pad;
+};
+
+struct BoxJob {
+  int n_boxes;
+  unsigned total_tiles;
+  int64_t total_cells;
+};
+
 struct IntParams {
   double p, dt, rtol, atol;
   int max_steps, q_max, fixed_T, fixed_step_n;
@@ -59,7 +77,11 @@ hipError_t launch_integrate(const DevMech& m, const IntParams& prm, double* T, d
                             int32_t* rec, hipStream_t stream);
 hipError_t launch_rates(const DevMech& m, double p, int fixed_T, const double* T, const double* Y, int64_t n,
                         double* wdot, double* f, double* jac, hipStream_t stream);
+hipError_t launch_boxes(const DevMech& m, const IntParams& prm, const BoxDev* boxes, const BoxJob* job,
+                        unsigned* head, int* remaining, int32_t* rec, int* host_done, int grid, hipStream_t stream);
 hipError_t launch_reduce_records(const int32_t* rec, int64_t n, unsigned long long* out, hipStream_t stream);
-size_t integrate_lds_bytes(int np_width, int N);
+hipError_t launch_reduce_records_job(const int32_t* rec, const BoxJob* job, unsigned long long* out,
+                                     hipStream_t stream);
+size_t integrate_lds_bytes(int np_width, int N, bool f32);
 
 }  // namespace chemgpu

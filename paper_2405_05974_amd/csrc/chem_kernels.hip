@@ -2,14 +2,17 @@
 //
 // Layout: one cell per group of NP lanes (NP = 16, 32 or 64 >= S + 1), 64/NP
 // cells per wave, one wave per workgroup.  Lane r of a group owns component r
-// of the state y = (Y_1..Y_S, T) and row r of the cell's Newton matrix, held
-// in VGPRs.  Reactions are spread over the group's lanes (reaction j on lane
-// j mod NP, in chunks of NP); species concentrations and Gibbs energies are
-// exchanged through LDS, production rates are gathered per species lane in
-// reaction order, and the sparse part of the Jacobian is scattered into
-// LDS rows with f64 LDS atomics before each lane loads its row.  Group sums
-// and the pivot search use xor-butterfly shuffles, whose commutative adds
-// give every lane of the group the same bits, so group decisions never split.
+// of the state y = (Y_1..Y_S, T).  Reactions are spread over the group's
+// lanes (reaction j on lane j mod NP, in chunks of NP); species
+// concentrations and Gibbs energies are exchanged through LDS, production
+// rates are gathered per species lane in reaction order, and the sparse part
+// of the Jacobian is scattered into per-cell LDS rows with f64 LDS atomics.
+// The Newton matrix lives in those LDS rows between phases and is factored in
+// registers (one row per lane) with partial pivoting; the factors are stored
+// back in pivot order so that the triangular solves broadcast from fixed
+// lanes.  Group reductions, the pivot search and broadcasts use DPP inside
+// 16-lane rows and readlane across rows: every lane of a group computes the
+// same expression on the same operands, so group decisions never split.
 #include "chem_internal.h"
 
 #include <cfloat>
@@ -27,39 +30,179 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The lane index with its value hidden from the optimiser: comparisons on it
+// are then evaluated where they are used instead of being hoisted out of the
+// integration loop as live masks (an empty register-only asm statement).
+__device__ __forceinline__ int opaque_lane() {
+  int v = (int)(threadIdx.x & (kWave - 1));
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// ----------------------------------------------------------- cross-lane ops
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)dpp_i<CTRL>((int)(unsigned)b);
+  const unsigned hi = (unsigned)dpp_i<CTRL>((int)(unsigned)(b >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+constexpr int kRor8 = 0x128, kRor4 = 0x124, kRor2 = 0x122, kRor1 = 0x121;
+
+// Sum over the group (all lanes receive the same bits).
 template <int NP>
 __device__ __forceinline__ double gsum(double v) {
-#pragma unroll
-  for (int o = NP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  v += dpp_d<kRor8>(v);
+  v += dpp_d<kRor4>(v);
+  v += dpp_d<kRor2>(v);
+  v += dpp_d<kRor1>(v);
+  if constexpr (NP == 32) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const double a = readlane_d(v, 0) + readlane_d(v, 16);
+    const double b = readlane_d(v, 32) + readlane_d(v, 48);
+    v = lane < 32 ? a : b;
+  } else if constexpr (NP == 64) {
+    v = (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+  }
   return v;
 }
 
 template <int NP>
 __device__ __forceinline__ int gor(int v) {
-#pragma unroll
-  for (int o = NP / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+  v |= dpp_i<kRor8>(v);
+  v |= dpp_i<kRor4>(v);
+  v |= dpp_i<kRor2>(v);
+  v |= dpp_i<kRor1>(v);
+  if constexpr (NP == 32) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int a = __builtin_amdgcn_readlane(v, 0) | __builtin_amdgcn_readlane(v, 16);
+    const int b = __builtin_amdgcn_readlane(v, 32) | __builtin_amdgcn_readlane(v, 48);
+    v = lane < 32 ? a : b;
+  } else if constexpr (NP == 64) {
+    v = (__builtin_amdgcn_readlane(v, 0) | __builtin_amdgcn_readlane(v, 16)) |
+        (__builtin_amdgcn_readlane(v, 32) | __builtin_amdgcn_readlane(v, 48));
+  }
   return v;
 }
 
-// Largest value in the group, ties to the lowest lane index.
+// (v, idx) takes (ov, oi) if that is larger, ties to the lower index.
+__device__ __forceinline__ void take_best(double& v, int& idx, double ov, int oi) {
+  if (ov > v || (ov == v && oi < idx)) {
+    v = ov;
+    idx = oi;
+  }
+}
+
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(double& v, int& idx) {
+  const double ov = dpp_d<CTRL>(v);
+  const int oi = dpp_i<CTRL>(idx);
+  take_best(v, idx, ov, oi);
+}
+
+// Largest value over the group, ties to the lowest lane index.
 template <int NP>
 __device__ __forceinline__ void gargmax(double& v, int& idx) {
-#pragma unroll
-  for (int o = NP / 2; o > 0; o >>= 1) {
-    double ov = __shfl_xor(v, o);
-    int oi = __shfl_xor(idx, o);
-    if (ov > v || (ov == v && oi < idx)) {
-      v = ov;
-      idx = oi;
+  argmax_step<kRor8>(v, idx);
+  argmax_step<kRor4>(v, idx);
+  argmax_step<kRor2>(v, idx);
+  argmax_step<kRor1>(v, idx);
+  if constexpr (NP >= 32) {
+    double v0 = readlane_d(v, 0), v1 = readlane_d(v, 16), v2 = readlane_d(v, 32), v3 = readlane_d(v, 48);
+    int i0 = __builtin_amdgcn_readlane(idx, 0), i1 = __builtin_amdgcn_readlane(idx, 16);
+    int i2 = __builtin_amdgcn_readlane(idx, 32), i3 = __builtin_amdgcn_readlane(idx, 48);
+    take_best(v0, i0, v1, i1);
+    take_best(v2, i2, v3, i3);
+    if constexpr (NP == 32) {
+      const int lane = threadIdx.x & (kWave - 1);
+      v = lane < 32 ? v0 : v2;
+      idx = lane < 32 ? i0 : i2;
+    } else {
+      take_best(v0, i0, v2, i2);
+      v = v0;
+      idx = i0;
     }
   }
 }
 
+// Value of group lane k (a compile-time constant after unrolling) to every
+// lane of the group.
+template <int NP>
+__device__ __forceinline__ double gbcast(double v, const int k) {
+  if constexpr (NP == 16) {
+    switch (k) {
+      case 0: return dpp_d<0x150>(v);
+      case 1: return dpp_d<0x151>(v);
+      case 2: return dpp_d<0x152>(v);
+      case 3: return dpp_d<0x153>(v);
+      case 4: return dpp_d<0x154>(v);
+      case 5: return dpp_d<0x155>(v);
+      case 6: return dpp_d<0x156>(v);
+      case 7: return dpp_d<0x157>(v);
+      case 8: return dpp_d<0x158>(v);
+      case 9: return dpp_d<0x159>(v);
+      case 10: return dpp_d<0x15A>(v);
+      case 11: return dpp_d<0x15B>(v);
+      case 12: return dpp_d<0x15C>(v);
+      case 13: return dpp_d<0x15D>(v);
+      case 14: return dpp_d<0x15E>(v);
+      default: return dpp_d<0x15F>(v);
+    }
+  } else if constexpr (NP == 32) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const double a = readlane_d(v, k), b = readlane_d(v, 32 + k);
+    return lane < 32 ? a : b;
+  } else {
+    return readlane_d(v, k);
+  }
+}
+
+// Per-lane species constants (lane r < S holds species r; other lanes hold
+// neutral values), loaded once per kernel.
+struct Spc {
+  double W, a0, a1, hf, s0;
+};
+
+__device__ __forceinline__ Spc load_species(const DevMech& m, const int r) {
+  Spc c{1.0, 0.0, 0.0, 0.0, 0.0};
+  if (r < m.S) {
+    c.W = m.W[r];
+    c.a0 = m.a0[r];
+    c.a1 = m.a1[r];
+    c.hf = m.hf[r];
+    c.s0 = m.s0[r];
+  }
+  return c;
+}
+
+template <int NP>
+__device__ __forceinline__ float gbcastf(float v, const int k) {
+  // broadcast a float through the 64-bit path (exact: float -> double -> float)
+  return (float)gbcast<NP>((double)v, k);
+}
+
+// ------------------------------------------------------------------ LDS map
+
 // LDS carve-up for one wave (64/NP groups).  Reaction scratch is indexed by
-// wave lane, vectors by group base + species index.
+// wave lane, per-species vectors by group base + species index, and each
+// group owns NP matrix rows of NP+1 doubles.
 struct Shared {
-  double* J;      // [groups][N][ldj]
-  double* C;      // [64] concentrations
+  double* J;      // [groups][NP][ldj]: Jacobian rows, then the pivot-ordered LU factors
+  double* C;      // [64] concentrations (mol/cm^3)
   double* G;      // [64] G_k/(R T)
   double* H;      // [64] H_k, J/mol
   double* W;      // [64] molecular weights (written once per kernel)
@@ -67,14 +210,14 @@ struct Shared {
   double* isT;    // [64] 1 for the temperature column, else 0
   double* rq;     // [9][64]: Q, dQ/dT, q0, dQ/dC slots 0..5
   double* prow;   // [2][64] pivot row, double-buffered
-  int* perm;      // [64] lane holding the pivot of column k
+  int* perm;      // [64] lane whose row holds pivot k
+  float* F;       // [groups][NP][ldj] FP32 LU factors (mixed-precision option only)
+  float* prow32;  // [2][64] FP32 pivot row
   int ldj;
-  int N;
 };
 
-__device__ __forceinline__ Shared carve(double* smem, int N, int NP) {
+__device__ __forceinline__ Shared carve(double* smem, int NP, bool f32 = false) {
   Shared s;
-  s.N = N;
   s.ldj = NP + 1;
   s.C = smem;
   s.G = s.C + kWave;
@@ -86,21 +229,27 @@ __device__ __forceinline__ Shared carve(double* smem, int N, int NP) {
   s.prow = s.rq + 9 * kWave;
   s.perm = reinterpret_cast<int*>(s.prow + 2 * kWave);
   s.J = s.prow + 2 * kWave + kWave / 2;   // perm takes 64 ints = 32 doubles
+  const size_t jd = (size_t)(kWave / NP) * NP * (NP + 1);
+  s.F = f32 ? reinterpret_cast<float*>(s.J + jd) : nullptr;
+  s.prow32 = f32 ? s.F + jd : nullptr;
   return s;
 }
 
 }  // namespace
 
-size_t integrate_lds_bytes(int np_width, int N) {
+size_t integrate_lds_bytes(int np_width, int N, bool f32) {
+  (void)N;
   const int groups = kWave / np_width;
-  const size_t doubles = 6 * kWave + 9 * kWave + 2 * kWave + kWave / 2 + (size_t)groups * N * (np_width + 1);
-  return doubles * sizeof(double);
+  const size_t jd = (size_t)groups * np_width * (np_width + 1);
+  const size_t doubles = 6 * kWave + 9 * kWave + 2 * kWave + kWave / 2 + jd;
+  return doubles * sizeof(double) + (f32 ? (jd + 2 * kWave) * sizeof(float) : 0);
 }
 
 namespace {
 
-// Right-hand side of the constant-pressure adiabatic reactor (and, with JAC,
-// lane r's row of J = df/dy) for the group's cell at state component yr.
+// Right-hand side of the constant-pressure adiabatic reactor for the group's
+// cell at state component yr; with JAC also J = df/dy, left in the group's
+// LDS rows (row r = lane r's row; padding rows zero).
 //   Eq. 2: Q_j = k_f prod C^nu' - k_r prod C^nu''   (times [M] for third body)
 //   Eq. 3: wdot_k = sum_j nu_kj Q_j
 //   dY_k/dt = W_k wdot_k / rho,  dT/dt = -sum H_k wdot_k / sum C_k Cp_k
@@ -109,28 +258,21 @@ namespace {
 // rank-1 part of [M] (unit efficiencies), the closed-form T derivatives, and
 // the chain rule through C_k(Y, T) and rho(Y, T).
 template <int NP, bool JAC>
-__device__ __forceinline__ void rhs_eval(const DevMech& m, const double p, const int fixedT, const double yr,
-                                         double& fr, double& wd_out, double (&jrow)[NP], const Shared& sh) {
-  const int lane = threadIdx.x & (kWave - 1);
+__device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const double p, const int fixedT,
+                                         const double yr, double& fr, double& wd_out, const Shared& sh) {
+  const int lane = opaque_lane();
   const int r = lane % NP;
   const int g = lane / NP;
   const int base = g * NP;
   const int S = m.S;
   const bool isSp = r < S;
-  double* Jg = sh.J + (size_t)g * sh.N * sh.ldj;
+  double* Jg = sh.J + (size_t)g * NP * sh.ldj;
 
   const double T = __shfl(yr, base + S);
   const double lnT = log(T);
   const double invT = 1.0 / T;
 
-  double W = 1.0, a0 = 0.0, a1 = 0.0, hf = 0.0, s0 = 0.0;
-  if (isSp) {
-    W = m.W[r];
-    a0 = m.a0[r];
-    a1 = m.a1[r];
-    hf = m.hf[r];
-    s0 = m.s0[r];
-  }
+  const double W = sc.W, a0 = sc.a0, a1 = sc.a1, hf = sc.hf, s0 = sc.s0;
   const double Yr = isSp ? yr : 0.0;
   const double sumYW = gsum<NP>(Yr / W);
   const double Wbar = 1.0 / sumYW;
@@ -147,7 +289,7 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const double p, const
   sh.C[lane] = C;
   sh.G[lane] = Gd;
   sh.H[lane] = H;
-  if (JAC && isSp) {
+  if (JAC) {
 #pragma unroll
     for (int c = 0; c < NP; ++c) Jg[r * sh.ldj + c] = 0.0;
   }
@@ -164,11 +306,12 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const double p, const
 #pragma unroll
     for (int s = 0; s < kSlots; ++s) dq[s] = 0.0;
     if (j < m.R) {
-      const RxParams x = m.rx[j];
+      const RxParams& x = m.rx[j];
+      const int type = x.type, nr = x.nr, np = x.np;
       const double kinf = exp(x.lnA + x.b * lnT - x.EaR * invT);
       double dlnkf = (x.b + x.EaR * invT) * invT;
       double kf = kinf, dkfdM = 0.0;
-      if (x.type == 2) {
+      if (type == 2) {
         const double k0 = exp(x.lnA0 + x.b0 * lnT - x.EaR0 * invT);
         const double dlnk0 = (x.b0 + x.EaR0 * invT) * invT;
         const double Pr = k0 * Mconc / kinf;
@@ -176,30 +319,33 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const double p, const
         dlnkf = dlnkf + (dlnk0 - dlnkf) / (1.0 + Pr);
         dkfdM = k0 / ((1.0 + Pr) * (1.0 + Pr));
       }
+      int sp[kSlots];
+#pragma unroll
+      for (int s = 0; s < kSlots; ++s) sp[s] = x.sp[s];
       double cs[kSlots];
 #pragma unroll
-      for (int s = 0; s < kSlots; ++s) cs[s] = (x.sp[s] >= 0) ? sh.C[base + x.sp[s]] : 1.0;
+      for (int s = 0; s < kSlots; ++s) cs[s] = (sp[s] >= 0) ? sh.C[base + sp[s]] : 1.0;
       double pf = 1.0, pr = 1.0;
 #pragma unroll
       for (int s = 0; s < kMaxSide; ++s) {
-        if (s < x.nr) pf *= cs[s];
-        if (s < x.np) pr *= cs[kMaxSide + s];
+        if (s < nr) pf *= cs[s];
+        if (s < np) pr *= cs[kMaxSide + s];
       }
       double kr = 0.0, dkr = 0.0, dkrdM = 0.0;
       if (x.rev) {
         double sg = 0.0, shh = 0.0;
 #pragma unroll
         for (int s = 0; s < kMaxSide; ++s) {
-          if (s < x.np) {
-            sg += sh.G[base + x.sp[kMaxSide + s]];
-            shh += sh.H[base + x.sp[kMaxSide + s]];
+          if (s < np) {
+            sg += sh.G[base + sp[kMaxSide + s]];
+            if (JAC) shh += sh.H[base + sp[kMaxSide + s]];
           }
-          if (s < x.nr) {
-            sg -= sh.G[base + x.sp[s]];
-            shh -= sh.H[base + x.sp[s]];
+          if (s < nr) {
+            sg -= sh.G[base + sp[s]];
+            if (JAC) shh -= sh.H[base + sp[s]];
           }
         }
-        const int dnu = x.np - x.nr;
+        const int dnu = np - nr;
         // k_r = k_f / K_c,  K_c = exp(-sum nu G/RT) (p0/RT)^dnu
         const double ratio = exp(sg - dnu * lnc0);
         kr = kf * ratio;
@@ -209,26 +355,26 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const double p, const
           dkrdM = dkfdM * ratio;
         }
       }
-      const double mf = (x.type == 1) ? Mconc : 1.0;
+      const double mf = (type == 1) ? Mconc : 1.0;
       const double net = kf * pf - kr * pr;
       Q = mf * net;
       if (JAC) {
         dQdT = mf * (kf * dlnkf * pf - dkr * pr);
-        q0 = (x.type == 1) ? net : ((x.type == 2) ? dkfdM * pf - dkrdM * pr : 0.0);
+        q0 = (type == 1) ? net : ((type == 2) ? dkfdM * pf - dkrdM * pr : 0.0);
 #pragma unroll
         for (int s = 0; s < kMaxSide; ++s) {
-          if (s < x.nr) {
+          if (s < nr) {
             double t = 1.0;
 #pragma unroll
             for (int s2 = 0; s2 < kMaxSide; ++s2)
-              if (s2 != s && s2 < x.nr) t *= cs[s2];
+              if (s2 != s && s2 < nr) t *= cs[s2];
             dq[s] = mf * kf * t;
           }
-          if (s < x.np) {
+          if (s < np) {
             double t = 1.0;
 #pragma unroll
             for (int s2 = 0; s2 < kMaxSide; ++s2)
-              if (s2 != s && s2 < x.np) t *= cs[kMaxSide + s2];
+              if (s2 != s && s2 < np) t *= cs[kMaxSide + s2];
             dq[kMaxSide + s] = -mf * kr * t;
           }
         }
@@ -277,7 +423,7 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const double p, const
   wd_out = wd;
 
   if (JAC) {
-    // species rows: A_k. = sparse LDS part + rank-1 [M] part (read twice from LDS)
+    // species rows: A_k. = sparse LDS part + rank-1 [M] part
     double AC = 0.0;
     if (isSp)
       for (int c = 0; c < S; ++c) AC += (Jg[r * sh.ldj + c] + ak) * sh.C[base + c];
@@ -291,19 +437,20 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const double p, const
     double colsum = HA;
     if (isSp)
       for (int k = 0; k < S; ++k) colsum += sh.H[base + k] * Jg[k * sh.ldj + r];
-    const double fac = W / rho;
-    const double fw = W * wd / rho;
-    const double tT = fac * dwdT + fw * invT;
+    wave_sync();   // all column reads done before rows are overwritten
+    if (isSp) {
+      const double fac = W / rho;
+      const double fw = W * wd / rho;
+      const double tT = fac * dwdT + fw * invT;
 #pragma unroll
-    for (int c = 0; c < NP; ++c) {
-      // species column c: (W_r/rho) dwdot_r/dY_c + (W_r wdot_r/rho) Wbar/W_c; T column: tT
-      const double iWc = sh.iW[base + c];
-      const double v = fac * ((Jg[r * sh.ldj + c] + ak) * rho * iWc - Wbar * iWc * AC) + fw * Wbar * iWc +
-                       sh.isT[base + c] * tT;
-      jrow[c] = isSp ? v : 0.0;
+      for (int c = 0; c < NP; ++c) {
+        // species column c: (W_r/rho) dwdot_r/dY_c + (W_r wdot_r/rho) Wbar/W_c; T column: tT
+        const double iWc = sh.iW[base + c];
+        Jg[r * sh.ldj + c] = fac * ((Jg[r * sh.ldj + c] + ak) * rho * iWc - Wbar * iWc * AC) + fw * Wbar * iWc +
+                             sh.isT[base + c] * tT;
+      }
     }
-    wave_sync();   // all column and row reads done before row S is written
-    // temperature row, one column per lane, through LDS row S
+    // temperature row, one column per lane (lanes beyond S write 0)
     double tcol = 0.0;
     if (!fixedT) {
       if (isSp) {
@@ -316,30 +463,28 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const double p, const
         tcol = -dN / den + num * dD / (den * den);
       }
     }
-    Jg[S * sh.ldj + r] = tcol;   // lanes beyond S write 0
-    wave_sync();
-    if (r == S) {
-#pragma unroll
-      for (int c = 0; c < NP; ++c) jrow[c] = Jg[S * sh.ldj + c];
-    }
+    Jg[S * sh.ldj + r] = tcol;
     wave_sync();
   }
 }
 
-// In-place LU with partial pivoting of the group's matrix, one row per lane.
-// Rows are never moved: the lane whose row wins the pivot search of column k
-// (largest |a_rk| among unused rows, ties to the lowest row) records pos = k
-// and publishes its row through LDS; the other unused rows store their
-// multiplier in a[k] and update columns > k.  perm[k] names the pivot lane.
-// Returns 1/u_kk of the lane's own pivot in rdiag.
+// Newton matrix M = I - c J from the group's LDS rows, factored with partial
+// pivoting (largest |m_rk| among unused rows, ties to the lowest row) one row
+// per lane in registers; the pivot row of each column is published through
+// LDS.  On return the LDS rows hold the factors in pivot order (row k = L row
+// k below the diagonal, U row k on and above it), perm[k] names the lane whose
+// original row became row k, and rdiag = 1/u_rr for lane r's position.
 template <int NP>
-__device__ __forceinline__ void lu_factor(double (&a)[NP], int& pos, double& rdiag, const Shared& sh) {
-  const int lane = threadIdx.x & (kWave - 1);
+__device__ __forceinline__ void factor_newton_matrix(const Shared& sh, const double cfac, double& rdiag) {
+  const int lane = opaque_lane();
   const int r = lane % NP;
   const int base = lane - r;
+  double* Jg = sh.J + (size_t)(lane / NP) * NP * sh.ldj;
+  double a[NP];
+#pragma unroll
+  for (int c = 0; c < NP; ++c) a[c] = ((c == r) ? 1.0 : 0.0) - cfac * Jg[r * sh.ldj + c];
   bool used = false;
-  pos = -1;
-  double dg = 1.0;
+  int pos = -1;
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
     double cand = used ? -1.0 : fabs(a[k]);
@@ -350,7 +495,6 @@ __device__ __forceinline__ void lu_factor(double (&a)[NP], int& pos, double& rdi
     if (r == idx) {
       used = true;
       pos = k;
-      dg = a[k];
       sh.perm[base + k] = r;
 #pragma unroll
       for (int c = k; c < NP; ++c) prow[c] = a[c];
@@ -363,30 +507,132 @@ __device__ __forceinline__ void lu_factor(double (&a)[NP], int& pos, double& rdi
       for (int c = k + 1; c < NP; ++c) a[c] -= l * prow[c];
     }
   }
-  rdiag = 1.0 / dg;
+  // store the rows in pivot order (every lane pivots exactly once)
+  if (pos >= 0) {
+#pragma unroll
+    for (int c = 0; c < NP; ++c) Jg[pos * sh.ldj + c] = a[c];
+  }
+  wave_sync();
+  rdiag = 1.0 / Jg[r * sh.ldj + r];
 }
 
-// Solve M x = b with the factors of lu_factor; lane r holds b_r on entry and
-// returns x_r.
+// Solve M x = b with the pivot-ordered factors; lane r holds b_r (component
+// r) on entry and returns x_r.
 template <int NP>
-__device__ __forceinline__ double lu_solve(const double (&a)[NP], const int pos, const double rdiag, double b,
-                                           const Shared& sh) {
-  const int lane = threadIdx.x & (kWave - 1);
+__device__ __forceinline__ double lu_solve(const Shared& sh, const double rdiag, const double b) {
+  const int lane = opaque_lane();
   const int r = lane % NP;
   const int base = lane - r;
+  const double* Jg = sh.J + (size_t)(lane / NP) * NP * sh.ldj;
+  double z = __shfl(b, base + sh.perm[base + r]);   // b in pivot order
 #pragma unroll
-  for (int k = 0; k < NP; ++k) {
-    const int pl = sh.perm[base + k];
-    const double zk = __shfl(b, base + pl);
-    if (pos > k) b -= a[k] * zk;
+  for (int k = 0; k < NP - 1; ++k) {
+    const double zk = gbcast<NP>(z, k);
+    if (r > k) z -= Jg[r * sh.ldj + k] * zk;
   }
   double x = 0.0;
 #pragma unroll
   for (int k = NP - 1; k >= 0; --k) {
-    const int pl = sh.perm[base + k];
-    const double xk = __shfl(b * rdiag, base + pl);
-    if (pos < k) b -= a[k] * xk;
+    const double xk = gbcast<NP>(z * rdiag, k);
+    if (r < k) z -= Jg[r * sh.ldj + k] * xk;
     if (r == k) x = xk;
+  }
+  return x;
+}
+
+template <int NP>
+__device__ __forceinline__ double wrms(const double v, const double w, const int N) {
+  const double t = v * w;
+  return sqrt(gsum<NP>(t * t) / N);
+}
+
+// Mixed-precision option: the same pivoted factorisation of M = I - c J in
+// FP32 (M rounded from FP64), factors kept in FP32 LDS rows in pivot order;
+// J stays in FP64 for the refinement residuals.
+template <int NP>
+__device__ __forceinline__ void factor_newton_matrix_f32(const Shared& sh, const double cfac, float& rdiag) {
+  const int lane = opaque_lane();
+  const int r = lane % NP;
+  const int base = lane - r;
+  const double* Jg = sh.J + (size_t)(lane / NP) * NP * sh.ldj;
+  float* Fg = sh.F + (size_t)(lane / NP) * NP * sh.ldj;
+  float a[NP];
+#pragma unroll
+  for (int c = 0; c < NP; ++c) a[c] = (float)(((c == r) ? 1.0 : 0.0) - cfac * Jg[r * sh.ldj + c]);
+  bool used = false;
+  int pos = -1;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    double cand = used ? -1.0 : (double)fabsf(a[k]);
+    if (!(cand == cand)) cand = -1.0;
+    int idx = r;
+    gargmax<NP>(cand, idx);
+    float* prow = sh.prow32 + (k & 1) * kWave + base;
+    if (r == idx) {
+      used = true;
+      pos = k;
+      sh.perm[base + k] = r;
+#pragma unroll
+      for (int c = k; c < NP; ++c) prow[c] = a[c];
+    }
+    wave_sync();
+    if (!used) {
+      const float l = a[k] / prow[k];
+      a[k] = l;
+#pragma unroll
+      for (int c = k + 1; c < NP; ++c) a[c] -= l * prow[c];
+    }
+  }
+  if (pos >= 0) {
+#pragma unroll
+    for (int c = 0; c < NP; ++c) Fg[pos * sh.ldj + c] = a[c];
+  }
+  wave_sync();
+  rdiag = 1.0f / Fg[r * sh.ldj + r];
+}
+
+template <int NP>
+__device__ __forceinline__ double lu_solve_f32(const Shared& sh, const float rdiag, const double b) {
+  const int lane = opaque_lane();
+  const int r = lane % NP;
+  const int base = lane - r;
+  const float* Fg = sh.F + (size_t)(lane / NP) * NP * sh.ldj;
+  float z = (float)__shfl(b, base + sh.perm[base + r]);
+#pragma unroll
+  for (int k = 0; k < NP - 1; ++k) {
+    const float zk = gbcastf<NP>(z, k);
+    if (r > k) z -= Fg[r * sh.ldj + k] * zk;
+  }
+  float x = 0.0f;
+#pragma unroll
+  for (int k = NP - 1; k >= 0; --k) {
+    const float xk = gbcastf<NP>(z * rdiag, k);
+    if (r < k) z -= Fg[r * sh.ldj + k] * xk;
+    if (r == k) x = xk;
+  }
+  return (double)x;
+}
+
+// x with M x = b to FP64 accuracy from FP32 factors: x = LU32^-1 b, then
+// refinement sweeps x += LU32^-1 (b - M x) with the residual in FP64
+// (M x = x - c J x from the FP64 Jacobian rows), until the WRMS correction is
+// below 1e-8 or ir_max sweeps have run.
+template <int NP>
+__device__ __forceinline__ double solve_refined(const Shared& sh, const float rdiag, const double cfac, const double b,
+                                                const double w, const int N, const int ir_max, int& sweeps) {
+  const int lane = opaque_lane();
+  const int r = lane % NP;
+  const double* Jg = sh.J + (size_t)(lane / NP) * NP * sh.ldj;
+  double x = lu_solve_f32<NP>(sh, rdiag, b);
+  for (int s = 0; s < ir_max; ++s) {
+    double jx = 0.0;
+#pragma unroll
+    for (int c = 0; c < NP; ++c) jx += Jg[r * sh.ldj + c] * gbcast<NP>(x, c);
+    const double res = b - (x - cfac * jx);
+    const double dx = lu_solve_f32<NP>(sh, rdiag, res);
+    x += dx;
+    sweeps++;
+    if (wrms<NP>(dx, w, N) <= 1e-8) break;
   }
   return x;
 }
@@ -437,20 +683,14 @@ __device__ __forceinline__ void rescale(double (&D)[kQMax + 2], const int mdim, 
   }
 }
 
-template <int NP>
-__device__ __forceinline__ double wrms(const double v, const double w, const int N) {
-  const double t = v * w;
-  return sqrt(gsum<NP>(t * t) / N);
-}
-
 // Mixture enthalpy sum_k Y_k H_k(T)/W_k of the group's cell (J/g).
 template <int NP>
-__device__ __forceinline__ double mix_enthalpy(const DevMech& m, const double Yr, const double T, const int r) {
+__device__ __forceinline__ double mix_enthalpy(const DevMech& m, const Spc& sc, const double Yr, const double T,
+                                               const int r) {
   double v = 0.0;
   if (r < m.S) {
-    const double a0 = m.a0[r], a1 = m.a1[r];
-    const double Hk = m.hf[r] + kRu * (a0 * (T - kTref) + a1 * (T * T - kTref * kTref) * 0.5);
-    v = Yr * Hk / m.W[r];
+    const double Hk = sc.hf + kRu * (sc.a0 * (T - kTref) + sc.a1 * (T * T - kTref * kTref) * 0.5);
+    v = Yr * Hk / sc.W;
   }
   return gsum<NP>(v);
 }
@@ -458,14 +698,14 @@ __device__ __forceinline__ double mix_enthalpy(const DevMech& m, const double Yr
 // Temperature at which the mixture with composition Y has enthalpy h: the
 // positive root of gamma T^2 + beta T + (alpha - h) = 0 in cancellation-free form.
 template <int NP>
-__device__ __forceinline__ double temperature_from_h(const DevMech& m, const double Yr, const double h, const int r) {
+__device__ __forceinline__ double temperature_from_h(const DevMech& m, const Spc& sc, const double Yr, const double h,
+                                                     const int r) {
   double al = 0.0, be = 0.0, ga = 0.0;
   if (r < m.S) {
-    const double w = Yr / m.W[r];
-    const double a0 = m.a0[r], a1 = m.a1[r];
-    al = w * (m.hf[r] - kRu * a0 * kTref - kRu * a1 * kTref * kTref / 2.0);
-    be = w * kRu * a0;
-    ga = w * kRu * a1 / 2.0;
+    const double w = Yr / sc.W;
+    al = w * (sc.hf - kRu * sc.a0 * kTref - kRu * sc.a1 * kTref * kTref / 2.0);
+    be = w * kRu * sc.a0;
+    ga = w * kRu * sc.a1 / 2.0;
   }
   al = gsum<NP>(al);
   be = gsum<NP>(be);
@@ -474,7 +714,6 @@ __device__ __forceinline__ double temperature_from_h(const DevMech& m, const dou
   return 2.0 * c / (be + sqrt(be * be + 4.0 * ga * c));
 }
 
-template <int NP>
 __device__ __forceinline__ double pick(const double (&D)[kQMax + 2], const int j) {
   double v = 0.0;
 #pragma unroll
@@ -483,26 +722,31 @@ __device__ __forceinline__ double pick(const double (&D)[kQMax + 2], const int j
   return v;
 }
 
+template <int NP>
+__device__ __forceinline__ void init_shared_constants(const DevMech& m, const Shared& sh) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int r = lane % NP;
+  sh.W[lane] = (r < m.S) ? m.W[r] : 1.0;
+  sh.iW[lane] = (r < m.S) ? 1.0 / m.W[r] : 0.0;
+  sh.isT[lane] = (r == m.S) ? 1.0 : 0.0;
+}
+
 // Variable-order BDF over [0, dt] for the group's cell; the same decisions as
 // the oracle's per-cell integrator (predictor/corrector in backward
 // differences, Newton with a fresh Jacobian and LU per attempt, WRMS error
 // test, quasi-constant step size with order selection after k+2 steps, and
 // enthalpy projection of T after every accepted step).
-template <int NP>
-__global__ __launch_bounds__(kWave) void integrate_kernel(const DevMech m, const IntParams P, double* __restrict__ Tg,
-                                                          double* __restrict__ Yg, const int64_t n,
-                                                          int32_t* __restrict__ rec) {
-  extern __shared__ double smem[];
-  const Shared sh = carve(smem, m.N, NP);
+// One group integrates cell `cell` of the SoA arrays (Tg, Yg, n) over [0, dt];
+// its record goes to column rec_cell of the rec array with rec_n columns.
+template <int NP, bool F32>
+__device__ __forceinline__ void integrate_group(const DevMech& m, const IntParams& P, const double dt,
+                                                const Shared& sh, const Spc& sc, double* __restrict__ Tg,
+                                                double* __restrict__ Yg, const int64_t n, const int64_t cell,
+                                                int32_t* __restrict__ rec, const int64_t rec_n,
+                                                const int64_t rec_cell) {
   const int lane = threadIdx.x & (kWave - 1);
   const int r = lane % NP;
-  const int g = lane / NP;
   const int S = m.S, N = m.N;
-  const int64_t cell = (int64_t)blockIdx.x * (kWave / NP) + g;
-  if (cell >= n) return;   // whole groups leave together
-  sh.W[lane] = (r < S) ? m.W[r] : 1.0;
-  sh.iW[lane] = (r < S) ? 1.0 / m.W[r] : 0.0;
-  sh.isT[lane] = (r == S) ? 1.0 : 0.0;
 
   double y0 = 0.0;
   if (r < S) y0 = Yg[(int64_t)r * n + cell];
@@ -512,38 +756,36 @@ __global__ __launch_bounds__(kWave) void integrate_kernel(const DevMech m, const
   if (r == S && !(y0 > 0.0)) bad = 1;
   bad = gor<NP>(bad);
 
-  int status = 0, steps = 0, attempts = 0, nrhs = 0, njac = 0, nnewton = 0, netf = 0, nnnf = 0;
+  int status = 0, steps = 0, attempts = 0, nrhs = 0, njac = 0, nnewton = 0, netf = 0, nnnf = 0, nir = 0;
   if (bad) {
     status = 3;
   } else {
     const int fixedT = P.fixed_T;
     const bool fixed = P.fixed_step_n > 0;
     const int q_max = P.q_max < 1 ? 1 : (P.q_max > kQMax ? kQMax : P.q_max);
-
     double D[kQMax + 2];
 #pragma unroll
     for (int j = 0; j < kQMax + 2; ++j) D[j] = 0.0;
     D[0] = (r < N) ? y0 : 0.0;
     const double T0 = __shfl(y0, (lane - r) + S);
-    const double h0 = mix_enthalpy<NP>(m, D[0], T0, r);
-    double jrow[NP];
-    double dummy[NP];
+    const double h0 = mix_enthalpy<NP>(m, sc, D[0], T0, r);
     double f, wdx;
-    rhs_eval<NP, false>(m, P.p, fixedT, D[0], f, wdx, dummy, sh);
+    rhs_eval<NP, false>(m, sc, P.p, fixedT, D[0], f, wdx, sh);
     nrhs++;
     double w = (r < N) ? 1.0 / (P.rtol * fabs(D[0]) + P.atol) : 0.0;
     double h;
     if (fixed) {
-      h = P.dt / P.fixed_step_n;
+      h = dt / P.fixed_step_n;
     } else {
       const double nf = wrms<NP>(f, w, N);
-      h = P.dt;
-      if (nf * P.dt > 1.0) h = 1.0 / nf;
+      h = dt;
+      if (nf * dt > 1.0) h = 1.0 / nf;
     }
     D[1] = h * f;
     int k = 1, etf = 0, nk = 0;
     double t = 0.0;
-    while (t < P.dt) {
+    while (t < dt) {
+      const int rl = opaque_lane() % NP;   // lane-index tests stay inside the loop
       if (attempts >= P.max_steps) {
         status = 1;
         break;
@@ -552,8 +794,8 @@ __global__ __launch_bounds__(kWave) void integrate_kernel(const DevMech m, const
       bool last = false;
       if (fixed) {
         last = (steps + 1 == P.fixed_step_n);
-      } else if (t + 1.1 * h >= P.dt) {   // end exactly at dt (stretch up to 10% or shorten)
-        const double hn = P.dt - t;
+      } else if (t + 1.1 * h >= dt) {   // end exactly at dt (stretch up to 10% or shorten)
+        const double hn = dt - t;
         rescale(D, k + 1 <= q_max ? k + 1 : q_max, hn / h);
         h = hn;
         nk = 0;
@@ -563,7 +805,7 @@ __global__ __launch_bounds__(kWave) void integrate_kernel(const DevMech m, const
         status = 2;
         break;
       }
-      w = (r < N) ? 1.0 / (P.rtol * fabs(D[0]) + P.atol) : 0.0;
+      w = (rl < N) ? 1.0 / (P.rtol * fabs(D[0]) + P.atol) : 0.0;
       double pred = D[0], ss = 0.0;
 #pragma unroll
       for (int j = 1; j <= kQMax; ++j)
@@ -576,13 +818,12 @@ __global__ __launch_bounds__(kWave) void integrate_kernel(const DevMech m, const
       const double c = h / gk;
 
       double fp;
-      rhs_eval<NP, true>(m, P.p, fixedT, pred, fp, wdx, jrow, sh);
+      rhs_eval<NP, true>(m, sc, P.p, fixedT, pred, fp, wdx, sh);
       njac++;
-#pragma unroll
-      for (int cc = 0; cc < NP; ++cc) jrow[cc] = ((cc == r) ? 1.0 : 0.0) - c * jrow[cc];
-      int pos;
-      double rdiag;
-      lu_factor<NP>(jrow, pos, rdiag, sh);
+      double rdiag = 0.0;
+      float rdiag32 = 0.0f;
+      if constexpr (F32) factor_newton_matrix_f32<NP>(sh, c, rdiag32);
+      else factor_newton_matrix<NP>(sh, c, rdiag);
 
       double d = 0.0;
       bool conv = false;
@@ -594,12 +835,14 @@ __global__ __launch_bounds__(kWave) void integrate_kernel(const DevMech m, const
         if (it == 1) {
           fi = fp;   // f at pred + 0 was evaluated with the Jacobian
         } else {
-          rhs_eval<NP, false>(m, P.p, fixedT, pred + d, fi, wdx, dummy, sh);
+          rhs_eval<NP, false>(m, sc, P.p, fixedT, pred + d, fi, wdx, sh);
         }
         nrhs++;
         nnewton++;
-        const double b = (r < N) ? -(d - c * fi + psi) : 0.0;
-        const double delta = lu_solve<NP>(jrow, pos, rdiag, b, sh);
+        const double b = (rl < N) ? -(d - c * fi + psi) : 0.0;
+        double delta;
+        if constexpr (F32) delta = solve_refined<NP>(sh, rdiag32, c, b, w, N, P.ir_max, nir);
+        else delta = lu_solve<NP>(sh, rdiag, b);
         d += delta;
         const double nrm = wrms<NP>(delta, w, N);
         if (nrm <= ntol) {
@@ -636,26 +879,21 @@ __global__ __launch_bounds__(kWave) void integrate_kernel(const DevMech m, const
       }
       // accept: D_{k+2} = d - D_{k+1}, D_{k+1} = d, D_j += D_{j+1} for j = k..0
       {
-        const double Dk1 = pick<NP>(D, k + 1);
-        double Dn[kQMax + 2];
-#pragma unroll
-        for (int j = 0; j < kQMax + 2; ++j) Dn[j] = D[j];
+        const double Dk1 = pick(D, k + 1);
 #pragma unroll
         for (int j = 0; j < kQMax + 2; ++j) {
-          if (j == k + 2 && k < q_max) Dn[j] = d - Dk1;
-          if (j == k + 1) Dn[j] = d;
+          if (j == k + 2 && k < q_max) D[j] = d - Dk1;
+          if (j == k + 1) D[j] = d;
         }
 #pragma unroll
         for (int j = kQMax; j >= 0; --j)
-          if (j <= k) Dn[j] = Dn[j] + Dn[j + 1];
-#pragma unroll
-        for (int j = 0; j < kQMax + 2; ++j) D[j] = Dn[j];
+          if (j <= k) D[j] = D[j] + D[j + 1];
       }
       if (!fixedT) {
-        const double Tn = temperature_from_h<NP>(m, D[0], h0, r);
-        if (r == S) D[0] = Tn;
+        const double Tn = temperature_from_h<NP>(m, sc, D[0], h0, rl);
+        if (rl == S) D[0] = Tn;
       }
-      t = last ? P.dt : t + h;
+      t = last ? dt : t + h;
       steps++;
       nk++;
       etf = 0;
@@ -667,7 +905,7 @@ __global__ __launch_bounds__(kWave) void integrate_kernel(const DevMech m, const
         const double tk = 1.2 * pow(err, 1.0 / (k + 1));
         rr = tk > 0.1 ? 1.0 / tk : 10.0;
         if (k > 1) {
-          const double ekm1 = wrms<NP>(pick<NP>(D, k), w, N) / k;
+          const double ekm1 = wrms<NP>(pick(D, k), w, N) / k;
           const double tm = 1.3 * pow(ekm1, 1.0 / k);
           const double rm = tm > 0.1 ? 1.0 / tm : 10.0;
           if (rm > rr) {
@@ -676,7 +914,7 @@ __global__ __launch_bounds__(kWave) void integrate_kernel(const DevMech m, const
           }
         }
         if (k < q_max) {
-          const double ekp1 = wrms<NP>(pick<NP>(D, k + 2), w, N) / (k + 2);
+          const double ekp1 = wrms<NP>(pick(D, k + 2), w, N) / (k + 2);
           const double tp = 1.4 * pow(ekp1, 1.0 / (k + 2));
           const double rp = tp > 0.1 ? 1.0 / tp : 10.0;
           if (rp > rr) {
@@ -704,15 +942,87 @@ __global__ __launch_bounds__(kWave) void integrate_kernel(const DevMech m, const
     else if (r == S) Tg[cell] = D[0];
   }
   if (rec != nullptr && r == 0) {
-    rec[0 * n + cell] = status;
-    rec[1 * n + cell] = steps;
-    rec[2 * n + cell] = attempts;
-    rec[3 * n + cell] = nrhs;
-    rec[4 * n + cell] = njac;
-    rec[5 * n + cell] = nnewton;
-    rec[6 * n + cell] = netf;
-    rec[7 * n + cell] = nnnf;
+    int32_t* rc = rec + rec_cell;
+    rc[0 * rec_n] = status;
+    rc[1 * rec_n] = steps;
+    rc[2 * rec_n] = attempts;
+    rc[3 * rec_n] = nrhs;
+    rc[4 * rec_n] = njac;
+    rc[5 * rec_n] = nnewton;
+    rc[6 * rec_n] = netf;
+    rc[7 * rec_n] = nnnf;
+    rc[8 * rec_n] = nir;
   }
+}
+
+template <int NP, bool F32>
+__global__ __launch_bounds__(kWave) void integrate_kernel(const DevMech m, const IntParams P, double* __restrict__ Tg,
+                                                          double* __restrict__ Yg, const int64_t n,
+                                                          int32_t* __restrict__ rec) {
+  extern __shared__ double smem[];
+  const Shared sh = carve(smem, NP, F32);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int r = lane % NP;
+  const int64_t cell = (int64_t)blockIdx.x * (kWave / NP) + lane / NP;
+  if (cell >= n) return;   // whole groups leave together
+  init_shared_constants<NP>(m, sh);
+  const Spc sc = load_species(m, r);
+  integrate_group<NP, F32>(m, P, P.dt, sh, sc, Tg, Yg, n, cell, rec, n, cell);
+}
+
+// Persistent variant for many boxes of uneven size and step: each wave takes
+// (box, tile of 64/NP cells) items from a device counter until the queue is
+// empty.  Items follow the box order given by the host (largest boxes first);
+// the wave that finishes a box's last tile raises that box's flag in
+// host-mapped memory (for latency timing on the host).
+template <int NP, bool F32>
+__global__ __launch_bounds__(kWave) void boxes_kernel(const DevMech m, const IntParams P,
+                                                      const BoxDev* __restrict__ boxes, const BoxJob* __restrict__ job,
+                                                      unsigned* __restrict__ head, int* __restrict__ remaining,
+                                                      int32_t* __restrict__ rec, int* __restrict__ host_done) {
+  extern __shared__ double smem[];
+  const Shared sh = carve(smem, NP, F32);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int r = lane % NP;
+  const int g = lane / NP;
+  init_shared_constants<NP>(m, sh);
+  const Spc sc = load_species(m, r);
+  const int nbox = job->n_boxes;
+  const unsigned total = job->total_tiles;
+  const int64_t rec_n = job->total_cells;
+  for (;;) {
+    unsigned item = 0;
+    if (lane == 0) item = atomicAdd(head, 1u);
+    item = (unsigned)__builtin_amdgcn_readfirstlane((int)item);
+    if (item >= total) break;
+    int lo = 0, hi = nbox - 1;
+    while (lo < hi) {   // last box whose first tile is <= item
+      const int mid = (lo + hi + 1) >> 1;
+      if (boxes[mid].tile_pre <= (int64_t)item) lo = mid;
+      else hi = mid - 1;
+    }
+    const BoxDev bx = boxes[lo];
+    const int64_t c = ((int64_t)item - bx.tile_pre) * (kWave / NP) + g;
+    if (c < bx.n) integrate_group<NP, F32>(m, P, bx.dt, sh, sc, bx.T, bx.Y, bx.n, c, rec, rec_n, bx.cell_off + c);
+    if (lane == 0) {
+      const int left = atomicSub(&remaining[lo], 1);
+      if (left == 1 && host_done != nullptr) {
+        __threadfence_system();
+        host_done[bx.box_id] = 1;
+      }
+    }
+  }
+}
+
+// Queue counters for boxes_kernel: head = 0, remaining[i] = tiles of box i.
+__global__ void boxes_init_kernel(const BoxDev* __restrict__ boxes, const BoxJob* __restrict__ job,
+                                  unsigned* __restrict__ head, int* __restrict__ remaining) {
+  const int nbox = job->n_boxes;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nbox; i += gridDim.x * blockDim.x) {
+    const int64_t next = (i + 1 < nbox) ? boxes[i + 1].tile_pre : (int64_t)job->total_tiles;
+    remaining[i] = (int)(next - boxes[i].tile_pre);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *head = 0u;
 }
 
 template <int NP>
@@ -721,34 +1031,32 @@ __global__ __launch_bounds__(kWave) void rates_kernel(const DevMech m, const dou
                                                       const int64_t n, double* __restrict__ wdot,
                                                       double* __restrict__ fout, double* __restrict__ jac) {
   extern __shared__ double smem[];
-  const Shared sh = carve(smem, m.N, NP);
+  const Shared sh = carve(smem, NP);
   const int lane = threadIdx.x & (kWave - 1);
   const int r = lane % NP;
   const int g = lane / NP;
   const int S = m.S, N = m.N;
   const int64_t cell = (int64_t)blockIdx.x * (kWave / NP) + g;
   if (cell >= n) return;
-  sh.W[lane] = (r < S) ? m.W[r] : 1.0;
-  sh.iW[lane] = (r < S) ? 1.0 / m.W[r] : 0.0;
-  sh.isT[lane] = (r == S) ? 1.0 : 0.0;
+  init_shared_constants<NP>(m, sh);
+  const Spc sc = load_species(m, r);
   double y = 0.0;
   if (r < S) y = Yg[(int64_t)r * n + cell];
   else if (r == S) y = Tg[cell];
   double f, wd;
-  double jrow[NP];
-  if (jac != nullptr) rhs_eval<NP, true>(m, p, fixedT, y, f, wd, jrow, sh);
-  else rhs_eval<NP, false>(m, p, fixedT, y, f, wd, jrow, sh);
+  if (jac != nullptr) rhs_eval<NP, true>(m, sc, p, fixedT, y, f, wd, sh);
+  else rhs_eval<NP, false>(m, sc, p, fixedT, y, f, wd, sh);
   if (r < S) wdot[(int64_t)r * n + cell] = wd * 1.0e6;   // mol/(cm^3 s) -> mol/(m^3 s)
   if (fout != nullptr && r < N) fout[(int64_t)r * n + cell] = f;
   if (jac != nullptr && r < N) {
-#pragma unroll
-    for (int c = 0; c < NP; ++c)
-      if (c < N) jac[((int64_t)r * N + c) * n + cell] = jrow[c];
+    const double* Jg = sh.J + (size_t)g * NP * sh.ldj;
+    for (int c = 0; c < N; ++c) jac[((int64_t)r * N + c) * n + cell] = Jg[r * sh.ldj + c];
   }
 }
 
-__global__ void reduce_records_kernel(const int32_t* __restrict__ rec, const int64_t n,
-                                      unsigned long long* __restrict__ out) {
+__global__ void reduce_records_kernel(const int32_t* __restrict__ rec, int64_t n,
+                                      unsigned long long* __restrict__ out, const BoxJob* __restrict__ job) {
+  if (job != nullptr) n = job->total_cells;
   __shared__ unsigned long long part[kStatCount][256];
   unsigned long long acc[kStatCount];
 #pragma unroll
@@ -765,6 +1073,7 @@ __global__ void reduce_records_kernel(const int32_t* __restrict__ rec, const int
     acc[6] += (unsigned)rec[6 * n + c];
     acc[7] += (unsigned)rec[7 * n + c];
     acc[8] += (st != 0) ? 1u : 0u;
+    acc[9] += (unsigned)rec[8 * n + c];
   }
 #pragma unroll
   for (int i = 0; i < kStatCount; ++i) part[i][threadIdx.x] = acc[i];
@@ -801,8 +1110,14 @@ hipError_t launch_integrate_np(const DevMech& m, const IntParams& prm, double* T
                                int32_t* rec, hipStream_t stream) {
   const int cpw = kWave / NP;
   const int64_t blocks = (n + cpw - 1) / cpw;
-  const size_t lds = integrate_lds_bytes(NP, m.N);
-  hipLaunchKernelGGL(integrate_kernel<NP>, dim3((unsigned)blocks), dim3(kWave), lds, stream, m, prm, T, Y, n, rec);
+  const bool f32 = prm.lu_fp32 != 0;
+  const size_t lds = integrate_lds_bytes(NP, m.N, f32);
+  if (f32)
+    hipLaunchKernelGGL((integrate_kernel<NP, true>), dim3((unsigned)blocks), dim3(kWave), lds, stream, m, prm, T, Y,
+                       n, rec);
+  else
+    hipLaunchKernelGGL((integrate_kernel<NP, false>), dim3((unsigned)blocks), dim3(kWave), lds, stream, m, prm, T,
+                       Y, n, rec);
   return hipGetLastError();
 }
 
@@ -811,13 +1126,40 @@ hipError_t launch_rates_np(const DevMech& m, double p, int fixed_T, const double
                            double* wdot, double* f, double* jac, hipStream_t stream) {
   const int cpw = kWave / NP;
   const int64_t blocks = (n + cpw - 1) / cpw;
-  const size_t lds = integrate_lds_bytes(NP, m.N);
+  const size_t lds = integrate_lds_bytes(NP, m.N, false);
   hipLaunchKernelGGL(rates_kernel<NP>, dim3((unsigned)blocks), dim3(kWave), lds, stream, m, p, fixed_T, T, Y, n,
                      wdot, f, jac);
   return hipGetLastError();
 }
 
+template <int NP>
+hipError_t launch_boxes_np(const DevMech& m, const IntParams& prm, const BoxDev* boxes, const BoxJob* job,
+                           unsigned* head, int* remaining, int32_t* rec, int* host_done, int grid,
+                           hipStream_t stream) {
+  const bool f32 = prm.lu_fp32 != 0;
+  const size_t lds = integrate_lds_bytes(NP, m.N, f32);
+  hipLaunchKernelGGL(boxes_init_kernel, dim3(64), dim3(256), 0, stream, boxes, job, head, remaining);
+  if (f32)
+    hipLaunchKernelGGL((boxes_kernel<NP, true>), dim3(grid), dim3(kWave), lds, stream, m, prm, boxes, job, head,
+                       remaining, rec, host_done);
+  else
+    hipLaunchKernelGGL((boxes_kernel<NP, false>), dim3(grid), dim3(kWave), lds, stream, m, prm, boxes, job, head,
+                       remaining, rec, host_done);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_boxes(const DevMech& m, const IntParams& prm, const BoxDev* boxes, const BoxJob* job,
+                        unsigned* head, int* remaining, int32_t* rec, int* host_done, int grid,
+                        hipStream_t stream) {
+  switch (m.np_width) {
+    case 16: return launch_boxes_np<16>(m, prm, boxes, job, head, remaining, rec, host_done, grid, stream);
+    case 32: return launch_boxes_np<32>(m, prm, boxes, job, head, remaining, rec, host_done, grid, stream);
+    case 64: return launch_boxes_np<64>(m, prm, boxes, job, head, remaining, rec, host_done, grid, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_integrate(const DevMech& m, const IntParams& prm, double* T, double* Y, int64_t n, int32_t* rec,
                             hipStream_t stream) {
@@ -844,8 +1186,16 @@ hipError_t launch_reduce_records(const int32_t* rec, int64_t n, unsigned long lo
   if (n > 0) {
     int64_t blocks = (n + 255) / 256;
     if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(reduce_records_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, rec, n, out);
+    hipLaunchKernelGGL(reduce_records_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, rec, n, out,
+                       (const BoxJob*)nullptr);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_records_job(const int32_t* rec, const BoxJob* job, unsigned long long* out,
+                                     hipStream_t stream) {
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, stream, out, kStatCount);
+  hipLaunchKernelGGL(reduce_records_kernel, dim3(1024), dim3(256), 0, stream, rec, (int64_t)0, out, job);
   return hipGetLastError();
 }
 

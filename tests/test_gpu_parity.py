@@ -45,10 +45,10 @@ def gpu_integrate(chem, torch_dev, mech_text, T, Y, p, dt, rtol, atol, **opts):
     Tt = torch.tensor(np.asarray(T, dtype=np.float64), device=dev)
     Yt = torch.tensor(np.ascontiguousarray(Y, dtype=np.float64), device=dev)
     n = Tt.numel()
-    rec = torch.zeros((8, max(n, 1)), dtype=torch.int32, device=dev)[:, :n].contiguous() if n else None
+    rec = torch.zeros((9, max(n, 1)), dtype=torch.int32, device=dev)[:, :n].contiguous() if n else None
     st = gm.integrate(Tt, Yt, p, dt, rtol, atol, records=rec)
     torch.cuda.synchronize()
-    recs = rec.cpu().numpy() if n else np.zeros((8, 0), np.int32)
+    recs = rec.cpu().numpy() if n else np.zeros((9, 0), np.int32)
     return Tt.cpu().numpy(), Yt.cpu().numpy(), st, recs
 
 
@@ -258,3 +258,66 @@ def test_config2_full_box_sampled(chem, torch_dev):
     assert_parity(Tg[idx], Yg[:, idx], To, Yo, "config2 sample")
     assert np.abs(Yg.sum(axis=0) - 1).max() <= 1e-9
     assert np.isfinite(Tg).all() and (Tg > 0).all()
+
+
+# ------------------------------------------------------------ batched boxes
+
+def _boxes(m, n_boxes, seed, max_cells):
+    return synth.amr_boxes(m, n_boxes, seed, max_cells=max_cells)
+
+
+@pytest.mark.parametrize("width", [32, 64])
+def test_boxes_batch_equals_alone_and_oracle(chem, torch_dev, width):
+    torch, dev = torch_dev
+    m = synth.config_mechanism(4)
+    text = m.to_text()
+    bxs = _boxes(m, 9, synth.config_seed(4), 37)
+    say(f"boxes n={len(bxs)} width={width}")
+    gm = chem.Mechanism(text)
+    gm.set_options(group_width=width)
+    tens = [(torch.tensor(b.T, device=dev), torch.tensor(b.Y, device=dev), b.dt) for b in bxs]
+    st, ms = gm.integrate_boxes(tens, synth.P_ATM, 1e-8, 1e-12, box_ms=True)
+    torch.cuda.synchronize()
+    assert st["rc"] == 0 and st["n_cells"] == sum(b.T.size for b in bxs)
+    assert all(v >= 0 for v in ms)
+    for i, b in enumerate(bxs):
+        Tg, Yg, st1, rec = gpu_integrate(chem, torch_dev, text, b.T, b.Y, synth.P_ATM, b.dt, 1e-8, 1e-12,
+                                         group_width=width)
+        # same device code, same inputs: the batched result is the lone result bit for bit
+        assert np.array_equal(tens[i][0].cpu().numpy(), Tg) and np.array_equal(tens[i][1].cpu().numpy(), Yg)
+        if i < 3:
+            To, Yo, so = oracle_integrate(text, b.T, b.Y, synth.P_ATM, b.dt, 1e-8, 1e-12)
+            assert_parity(Tg, Yg, To, Yo, f"box {i}")
+
+
+def test_boxes_graph_replay_matches_direct(chem, torch_dev):
+    torch, dev = torch_dev
+    m = synth.config_mechanism(1)
+    bxs = _boxes(m, 12, 77, 29)
+    say("boxes graph vs direct, three replays")
+    gm = chem.Mechanism(m.to_text())
+    outs = []
+    for graph in (0, 1, 1, 1):
+        gm.set_options(graph=graph)
+        tens = [(torch.tensor(b.T, device=dev), torch.tensor(b.Y, device=dev), b.dt) for b in bxs]
+        st, _ = gm.integrate_boxes(tens, synth.P_ATM, 1e-8, 1e-12)
+        torch.cuda.synchronize()
+        outs.append([(t.cpu().numpy(), y.cpu().numpy()) for t, y, _ in tens])
+        # eager work between replays
+        torch.ones(1000, device=dev).sum().item()
+    for o in outs[1:]:
+        for (ta, ya), (tb, yb) in zip(outs[0], o):
+            assert np.array_equal(ta, tb) and np.array_equal(ya, yb)
+
+
+def test_fp32_lu_refined_matches_fp64(chem, torch_dev):
+    w = synth.config_workload(1, n=128)
+    text = w.mech.to_text()
+    say("lu_fp32 vs fp64, rtol 1e-6")
+    Tg, Yg, st, rec = gpu_integrate(chem, torch_dev, text, w.T, w.Y, w.p, 2e-6, 1e-6, 1e-12, lu_fp32=1)
+    To, Yo, so = oracle_integrate(text, w.T, w.Y, w.p, 2e-6, 1e-6, 1e-12)
+    assert st["n_ir_sweeps"] > 0 and (rec[8] > 0).all()
+    dY = np.abs(Yg - Yo).max()
+    dT = (np.abs(Tg - To) / To).max()
+    say(f"lu_fp32: max|dY|={dY:.3e} max|dT|/T={dT:.3e}")
+    assert dY <= 1e-6 and dT <= 1e-6

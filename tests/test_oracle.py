@@ -7,7 +7,7 @@ by re-typing the oracle's own formulas.
 * rates/integration: closed-form decays for elementary, third-body and
   Lindemann reactions, and the A <-> B relaxation
 * Jacobian (Eq. 7): complex-step derivative of an independent rhs, the paper's
-  Eq. 9 error metric against central differences, first-order convergence of
+  Eq. 10 error metric against central differences, first-order convergence of
   one-sided differences (App. C)
 * LU: numpy.linalg.solve; enthalpy inversion: numpy.roots
 * integrator: conservation of elements, sum(Y) and enthalpy; detailed balance
@@ -287,7 +287,7 @@ def test_jacobian_eq9_and_one_sided_fd_order(g10):
             ym[j] -= e
             Jfd[:, j] = (om.rhs(yp, P) - om.rhs(ym, P)) / (2 * e)
         errs.append(np.linalg.norm(J - Jfd) / np.linalg.norm(Jfd))
-    assert np.mean(errs) < 1e-5          # Eq. 9 with central differences
+    assert np.mean(errs) < 1e-5          # Eq. 10 with central differences
     # App. C: one-sided differences approach the analytic Jacobian at first order
     y = state(m, 1300.0, 5)
     J = om.jac(y, P)
