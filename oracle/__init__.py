@@ -37,7 +37,8 @@ class OrcOpts(C.Structure):
 
 class OrcCellStats(C.Structure):
     _fields_ = [("status", C.c_int), ("steps", C.c_int), ("attempts", C.c_int), ("n_rhs", C.c_int),
-                ("n_jac", C.c_int), ("n_newton", C.c_int), ("n_etf", C.c_int), ("n_nnf", C.c_int)]
+                ("n_jac", C.c_int), ("n_newton", C.c_int), ("n_etf", C.c_int), ("n_nnf", C.c_int),
+                ("n_clip", C.c_int), ("clip_mass", C.c_double)]
 
 
 _lib = None
@@ -169,7 +170,9 @@ class Mech:
                                C.byref(o), st, int(nthreads))
         stats = None
         if want_stats:
-            dt_ = np.dtype([(name, np.int32) for name, _ in OrcCellStats._fields_])
+            dt_ = np.dtype([(name, np.float64 if ty is C.c_double else np.int32)
+                            for name, ty in OrcCellStats._fields_], align=True)
+            assert dt_.itemsize == C.sizeof(OrcCellStats)
             stats = np.frombuffer(st, dtype=dt_).copy()
         return T, Y, stats
 

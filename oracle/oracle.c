@@ -24,8 +24,8 @@
  *       dY_k/dt = W_k wdot_k / rho,  dT/dt = -sum_k H_k wdot_k / sum_k C_k Cp_k
  *   - species thermo with linear heat capacity cp/R = a0 + a1 T.
  *   - quasi-constant-step BDF in backward-difference form, orders 1-5, a
- *     fresh Jacobian and LU every step, WRMS error control, and projection of
- *     T onto the initial mixture enthalpy after every accepted step.
+ *     fresh Jacobian and LU every step, WRMS error control, and after every
+ *     accepted step projection of Y onto Y >= 0.
  * Units: the interface is SI (K, Pa, s, mass fractions); concentrations and
  * rate constants are cgs (mol/cm^3, A in mol-cm-s units).
  *
@@ -483,15 +483,27 @@ typedef struct {
 typedef struct {
   int status;          /* 0 ok, 1 max_steps, 2 step size underflow, 3 bad input */
   int steps, attempts, n_rhs, n_jac, n_newton, n_etf, n_nnf;
+  int n_clip;          /* mass fractions set to zero by the positivity projection */
+  double clip_mass;    /* their total magnitude (the mass the projection added) */
 } orc_cell_stats;
 
 #define ORC_QMAX 5
 
-/* WRMS norm over all N components with weights w. */
+/* WRMS norm over all N components with weights w: sqrt(sum (v_i w_i)^2 / n).
+ * Cold cells can have right-hand sides near 1e240, whose squares overflow;
+ * when the plain sum is not finite the same norm is taken as
+ * M sqrt(sum (v_i w_i / M)^2 / n) with M = max |v_i w_i|. */
 static double orc_wrms(int n, const double *v, const double *w) {
   double s = 0.0;
   for (int i = 0; i < n; ++i) s += (v[i] * w[i]) * (v[i] * w[i]);
-  return sqrt(s / n);
+  if (isfinite(s)) return sqrt(s / n);
+  double M = 0.0;
+  for (int i = 0; i < n; ++i)
+    if (fabs(v[i] * w[i]) > M) M = fabs(v[i] * w[i]);
+  if (!isfinite(M)) return M;
+  s = 0.0;
+  for (int i = 0; i < n; ++i) s += (v[i] * w[i] / M) * (v[i] * w[i] / M);
+  return M * sqrt(s / n);
 }
 
 /* Change the step size by the ratio r: the backward differences D_1..D_m of
@@ -545,9 +557,16 @@ static void orc_rescale(int n, double **D, int mdim, double r) {
  * An error test failure shrinks h by max(0.2, 0.9 e^(-1/(k+1))); three in a
  * row drop to order 1 with h /= 10.  When t + 1.1 h reaches dt the step is set
  * to end exactly at dt.  Every change of h rescales the
- * differences D_1..D_{min(k+1,q_max)}.  After every accepted step T is reset
- * so that the mixture enthalpy equals its initial value (adiabatic, constant
- * pressure). */
+ * differences D_1..D_{min(k+1,q_max)}.  After every accepted step, a mass
+ * fraction that came out negative is set to zero together with all of its
+ * backward differences (projection onto Y >= 0, Sandu 2001: with reverse rate
+ * constants as large as these, a species left below zero drives reactions
+ * that share it on both sides backwards and the solution runs away; the reset
+ * differences make the next predictor hold it at zero).  T is integrated
+ * through its own equation and is not projected: moving T after a step moves
+ * the fast partial equilibria with it, and the next step then sees a jump no
+ * step size above the round-off floor can resolve.  The mixture enthalpy is
+ * therefore conserved to the integration tolerance. */
 static void orc_integrate_cell(const orc_mech *m, double *y, double p, double dt, double rtol, double atol,
                                const orc_opts *o, orc_cell_stats *st) {
   int S = m->S, N = S + 1;
@@ -567,7 +586,6 @@ static void orc_integrate_cell(const orc_mech *m, double *y, double p, double dt
   double T0 = y[S];
   if (!(T0 > 0.0) || !isfinite(T0) || !(dt > 0.0)) { st->status = 3; goto out; }
   for (int k = 0; k < S; ++k) if (!isfinite(y[k])) { st->status = 3; goto out; }
-  double h0 = orc_enthalpy(m, T0, y);
   for (int j = 0; j < ORC_QMAX + 3; ++j) for (int i = 0; i < N; ++i) D[j][i] = 0.0;
   for (int i = 0; i < N; ++i) D[0][i] = y[i];
   orc_rhs(m, D[0], p, fixedT, f);
@@ -663,7 +681,12 @@ static void orc_integrate_cell(const orc_mech *m, double *y, double p, double dt
     for (int i = 0; i < N; ++i) D[k + 1][i] = d[i];
     for (int j = k; j >= 0; --j)
       for (int i = 0; i < N; ++i) D[j][i] += D[j + 1][i];
-    if (!fixedT) D[0][S] = orc_temperature_from_h(m, h0, D[0]);
+    for (int i = 0; i < S; ++i)
+      if (D[0][i] < 0.0) {
+        st->n_clip++;
+        st->clip_mass -= D[0][i];
+        for (int j = 0; j < ORC_QMAX + 3; ++j) D[j][i] = 0.0;
+      }
     t = last ? dt : t + h;
     st->steps++;
     nk++;

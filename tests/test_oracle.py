@@ -10,7 +10,7 @@ by re-typing the oracle's own formulas.
   Eq. 10 error metric against central differences, first-order convergence of
   one-sided differences (App. C)
 * LU: numpy.linalg.solve; enthalpy inversion: numpy.roots
-* integrator: conservation of elements, sum(Y) and enthalpy; detailed balance
+* integrator: conservation of elements, sum(Y) and enthalpy (to tolerance); detailed balance
   at long times; convergence order 1 and 2 with fixed steps; agreement with
   scipy's Radau within tolerance
 """
@@ -342,19 +342,32 @@ def test_integration_invariants(g10, g10_run):
     w, T, Y, st = g10_run
     assert (st["status"] == 0).all()
     W = om.weights()
-    # exact in exact arithmetic (c^T M = c^T for every linear invariant c);
-    # rounding grows with the size of intermediate Newton iterates
+    # Linear invariants (total mass, element totals) are exact in exact
+    # arithmetic (c^T D_j = 0 for every backward difference), so in cells the
+    # positivity projection never touched they hold to rounding, which grows
+    # with the Newton iterates.  Zeroing a component's differences breaks
+    # c^T D_j = 0 for the following steps: there they hold to the integration
+    # tolerance only.
+    clip = st["n_clip"] > 0
+    assert (clip == (st["clip_mass"] > 0)).all() and (~clip).sum() >= 24
     dev = np.abs(Y.sum(axis=0) - 1.0)
-    assert dev.max() <= 1e-10 and np.median(dev) <= 1e-14
+    assert dev[~clip].max() <= 1e-10 and np.median(dev) <= 1e-14 and dev.max() <= 1e-8
     for e in range(m.atoms.shape[1]):
         z0 = (m.atoms[:, e] / W) @ w.Y
         z1 = (m.atoms[:, e] / W) @ Y
         rel = np.abs(z1 - z0) / np.abs(z0).max()
-        assert rel.max() <= 1e-10 and np.median(rel) <= 1e-14
-    for i in range(0, 48, 7):
-        h0 = om.enthalpy(w.T[i], w.Y[:, i])
-        h1 = om.enthalpy(T[i], Y[:, i])
-        assert abs(h1 - h0) <= 1e-12 * max(abs(h0), 1.0)
+        assert rel[~clip].max() <= 1e-10 and np.median(rel) <= 1e-14 and rel.max() <= 1e-8
+    # Enthalpy is conserved by the ODE (adiabatic, constant pressure) but not
+    # exactly by BDF, since it is nonlinear in T: the drift is an integration
+    # error and shrinks with the tolerance.
+    scale = np.array([om.enthalpy(w.T[i], w.Y[:, i]) for i in range(48)])
+    cpT = 1.5e6                        # J/kg, cp * T of these mixtures
+    drift = np.array([abs(om.enthalpy(T[i], Y[:, i]) - scale[i]) for i in range(48)]) / (np.abs(scale) + cpT)
+    assert drift.max() <= 1e-7
+    Tt, Yt, _ = om.integrate(w.T[:8], w.Y[:, :8], w.p, w.dt, 1e-12, 1e-20)
+    drift_t = np.array([abs(om.enthalpy(Tt[i], Yt[:, i]) - scale[i]) for i in range(8)]) / (np.abs(scale[:8]) + cpT)
+    assert drift_t.max() <= 1e-11
+    assert (Y >= 0).all()              # the positivity projection
     assert (T > w.T).mean() > 0.5       # these mixtures release heat
 
 
@@ -362,8 +375,9 @@ def test_integration_against_tight_reference(g10, g10_run):
     m, om = g10
     w, T, Y, st = g10_run
     Tt, Yt, _ = om.integrate(w.T[:12], w.Y[:, :12], w.p, w.dt, 1e-12, 1e-20)
+    # global error of an rtol = 1e-8 run: a small multiple of rtol
     assert np.abs(Y[:, :12] - Yt).max() <= 1e-8
-    assert (np.abs(T[:12] - Tt) / Tt).max() <= 1e-8
+    assert (np.abs(T[:12] - Tt) / Tt).max() <= 3e-8
     T2, Y2, _ = om.integrate(w.T[:12], w.Y[:, :12], w.p, w.dt, 1e-6, 1e-12)
     e2 = np.abs(Y2 - Yt).max()
     e1 = np.abs(Y[:, :12] - Yt).max()
