@@ -55,6 +55,16 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2048, help="cells in the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--q-max", type=int, default=5)
+    ap.add_argument("--mode", choices=["flame", "boxes", "serve", "copy"], default="flame",
+                    help="flame: the headline box; boxes: uneven AMR boxes in one persistent launch; "
+                         "serve: Poisson request trace through the continuous-batching server; "
+                         "copy: a plain device copy of known size (HBM counter calibration)")
+    ap.add_argument("--lu-fp32", action="store_true", help="FP32 Newton-matrix LU with FP64 refinement")
+    ap.add_argument("--n-boxes", type=int, default=200)
+    ap.add_argument("--max-box-cells", type=int, default=4096)
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve: arrivals per second")
+    ap.add_argument("--duration", type=float, default=5.0, help="serve: trace length, s")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -65,6 +75,12 @@ def main():
     from paper_2405_05974_amd import chem, synth
 
     dev = torch.device("cuda:0")
+    if args.mode == "copy":
+        return copy_calibration(torch, dev)
+    if args.mode == "boxes":
+        return bench_boxes(args, torch, dev, chem, synth)
+    if args.mode == "serve":
+        return bench_serve(args, torch, dev, chem, synth)
     shape = tuple(int(v) for v in args.shape.split(","))
     w = synth.config_workload(2, os.path.join(ROOT, "tests", "golden"), shape=shape)
     m = w.mech
@@ -72,7 +88,7 @@ def main():
     n_tb = sum(r.kind == 1 for r in m.reactions)
     n_fo = sum(r.kind == 2 for r in m.reactions)
     gm = chem.Mechanism(m.to_text())
-    gm.set_options(q_max=args.q_max)
+    gm.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32))
     T0 = torch.tensor(w.T, dtype=torch.float64, device=dev)
     Y0 = torch.tensor(w.Y, dtype=torch.float64, device=dev)
     T = torch.empty_like(T0)
@@ -117,7 +133,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64+f32lu" if args.lu_fp32 else "f64",
         "data": "synthetic",
         "config": {
             "workload": (f"planar flame box {shape[0]}x{shape[1]}x{shape[2]} = {n} cells, mechanism "
@@ -163,6 +179,109 @@ def cpu_baseline(w, Tg, Yg, args):
     base = {"value": idx.size / el, "unit": "cells/s", "cores": threads, "kind": "oracle",
             "sample": f"{idx.size} cells evenly strided over the {n}-cell box ({el:.1f} s)"}
     return base, acc
+
+
+def copy_calibration(torch, dev):
+    """A plain device copy of 256 MiB, three times: the FETCH_SIZE and
+    WRITE_SIZE counters of its dispatches against the known bytes give the
+    scale factor applied to the integration kernel's counters."""
+    n = (256 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copy", "bytes_read_per_dispatch": n * 8, "bytes_written_per_dispatch": n * 8}))
+
+
+def bench_boxes(args, torch, dev, chem, synth):
+    """Uneven AMR boxes of G(30,180,4, seed 3) with per-box dt, one persistent
+    launch; edges log-uniform 8..64 cells, capped at --max-box-cells."""
+    m = synth.config_mechanism(4)
+    boxes = synth.amr_boxes(m, args.n_boxes, synth.config_seed(4), max_cells=args.max_box_cells)
+    gm = chem.Mechanism(m.to_text())
+    gm.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32))
+    src = [(torch.tensor(b.T, device=dev), torch.tensor(b.Y, device=dev), b.dt) for b in boxes]
+    work = [(t.clone(), y.clone(), dt) for t, y, dt in src]
+    sample_T = torch.cat([t[: min(256, t.numel())] for t, _, _ in src[:8]])
+    sample_Y = torch.cat([y[:, : min(256, y.shape[1])] for _, y, _ in src[:8]], dim=1).contiguous()
+    width, waves = gm.autotune(sample_T, sample_Y, synth.P_ATM, float(np.median([b.dt for b in boxes])), 1e-8, 1e-12)
+    n = sum(b.T.size for b in boxes)
+
+    def reset():
+        for (t, y, _), (t0, y0, _) in zip(work, src):
+            t.copy_(t0)
+            y.copy_(y0)
+
+    for _ in range(args.warmup):
+        reset()
+        gm.integrate_boxes(work, synth.P_ATM, 1e-8, 1e-12)
+    times, lat, stats = [], [], None
+    for i in range(args.steps):
+        reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats, ms = gm.integrate_boxes(work, synth.P_ATM, 1e-8, 1e-12, box_ms=True)
+        times.append(time.perf_counter() - t0)
+        lat.extend(ms)
+        print(f"boxes step {i}: {times[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    el = float(np.median(times))
+    print(json.dumps({
+        "mode": "boxes", "metric": METRIC, "value": n / el, "unit": "cells/s", "n_gpus": 1,
+        "steps": args.steps, "ms_per_step": el * 1e3, "dtype": "f64+f32lu" if args.lu_fp32 else "f64",
+        "box_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "what": "launch to box completion, host-observed"},
+        "config": {"workload": f"{len(boxes)} boxes of G(30,180,4,seed 3), edges log-uniform 8..64 capped at "
+                               f"{args.max_box_cells} cells, per-box dt log-uniform 1e-7..1e-5 s, rtol 1e-8",
+                   "cells": n, "group_width": width, "waves_per_cu": waves},
+        "integration": {"steps_per_cell": stats["n_steps_total"] / n, "failed_cells": stats["n_cells_failed"]},
+    }), flush=True)
+
+
+def bench_serve(args, torch, dev, chem, synth):
+    """Poisson arrivals of box-solve requests, each drawing G(10,25,3,s1) or
+    G(53,325,4,s2) with p = 0.5 and an edge log-uniform in 8..64 cells
+    (capped at --max-box-cells); T, Y and dt as in the uneven-box workload."""
+    mechs_ = [synth.config_mechanism(2), synth.config_mechanism(3)]
+    handles = [chem.Mechanism(m.to_text()) for m in mechs_]
+    for h in handles:
+        h.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32))
+    arrivals = synth.poisson_trace(1005, args.rate, args.duration)
+    rng = np.random.default_rng(1005)
+    reqs = []
+    for i, ta in enumerate(arrivals):
+        k = int(rng.integers(0, 2))
+        bx = synth.amr_boxes(mechs_[k], 1, 10_000 + i, max_cells=args.max_box_cells)[0]
+        reqs.append((ta, k, bx))
+    srv = chem.Server(int(args.budget_gb * (1 << 30)), streams=4)
+    pending, lat, cells = {}, [], 0
+    t0 = time.perf_counter()
+    i = 0
+    while i < len(reqs) or pending:
+        now = time.perf_counter() - t0
+        while i < len(reqs) and reqs[i][0] <= now:
+            ta, k, bx = reqs[i]
+            pending[srv.submit(handles[k], bx.T, bx.Y, synth.P_ATM, bx.dt, 1e-8, 1e-12)] = bx.T.size
+            i += 1
+        for rid in list(pending):
+            r = srv.poll(rid)
+            if r is not None:
+                lat.append(r[2])
+                cells += pending.pop(rid)
+        time.sleep(0.0005)
+    el = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    print(json.dumps({
+        "mode": "serve", "metric": METRIC, "value": cells / el, "unit": "cells/s", "n_gpus": 1,
+        "dtype": "f64+f32lu" if args.lu_fp32 else "f64",
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "what": "request arrival to results on the host"},
+        "config": {"workload": f"Poisson {args.rate:g} req/s for {args.duration:g} s, mechanisms G(10,25,3,s1) | "
+                               f"G(53,325,4,s2) p=0.5, edges 8..64 capped at {args.max_box_cells} cells",
+                   "requests": len(reqs), "budget_gb": args.budget_gb},
+        "server": st, "wall_s": el,
+    }), flush=True)
 
 
 if __name__ == "__main__":

@@ -72,7 +72,7 @@ typedef struct {
 /* Option keys for chem_set_option (values are passed as double). */
 #define CHEM_OPT_MAX_STEPS 1    /* step attempts per cell, default 100000 */
 #define CHEM_OPT_Q_MAX 2        /* highest BDF order 1..5, default 5 */
-#define CHEM_OPT_FIXED_T 3      /* 1: hold T constant (dT/dt = 0, no enthalpy projection); default 0 */
+#define CHEM_OPT_FIXED_T 3      /* 1: hold T constant (dT/dt = 0); default 0 */
 #define CHEM_OPT_FIXED_STEP 4   /* n > 0: n equal steps, no error test (convergence studies); default 0 */
 #define CHEM_OPT_LU_FP32 5      /* 1: factorise the Newton matrix in FP32 with FP64 residual refinement */
 #define CHEM_OPT_IR_MAX 6       /* refinement sweeps per solve for CHEM_OPT_LU_FP32, default 3 */
@@ -109,7 +109,10 @@ int chem_set_option(chem_mech* m, int key, double value);
 /* Integrate n_cells reactors in place over [0, dt] at pressure p.
  * T[n_cells] and Y[S * n_cells] (device, SoA) are read and overwritten with
  * the state at dt.  rtol > 0, atol >= 0 set the WRMS error weights
- * 1/(rtol |y| + atol) used for every component, T included.  stats (host
+ * 1/(rtol |y| + atol) used for every component, T included.  A mass
+ * fraction that a step leaves negative is set to zero (outputs are >= 0);
+ * T follows its own equation, so the mixture enthalpy is conserved to the
+ * integration tolerance.  stats (host
  * pointer, may be NULL) receives the totals.  Returns CHEM_OK,
  * CHEM_WARN_CELLS_FAILED if any cell failed (see the CHEM_CELL_* codes), or
  * an error code.  n_cells == 0 is a no-op returning CHEM_OK. */
@@ -143,6 +146,63 @@ typedef struct {
  * Returns as chem_integrate. */
 int chem_integrate_boxes(chem_mech* m, int n_boxes, const chem_box* boxes, double p, double rtol, double atol,
                          chem_stats* stats, double* box_ms);
+
+/* Pick the lanes-per-cell group width (16/32/64, at least S+1) and the
+ * persistent grid's waves per CU (4, 8, 12, 16) for this mechanism by timing
+ * chem_integrate_boxes on scratch copies of a caller-supplied sample (device
+ * T[n], Y[S*n], left unchanged; split into boxes of up to 4096 cells), and
+ * set them on the handle.  The choice only changes speed: results are the
+ * same for every candidate.  Choices are cached per (device, S, R) for the
+ * process; best_width/best_waves (may be NULL) receive the choice. */
+int chem_autotune(chem_mech* m, int64_t n_cells, const double* T, const double* Y, double p, double dt, double rtol,
+                  double atol, int* best_width, int* best_waves);
+
+/* ------------------------------------------------------------ serving ---
+ * A continuous-batching request server.  Clients submit box-solve requests
+ * (host arrays, any loaded mechanism, own dt/tolerances) at any time; a
+ * dispatcher thread admits them in arrival order while their device memory
+ * fits in the HBM budget, and launches everything admitted since the previous
+ * launch as one batched launch per mechanism on one of `streams` streams, so
+ * requests that arrive while others run overlap with them on the device.
+ * Results come back to pinned host memory; latency is arrival (submit) to
+ * results on the host.  The handles passed to submit must stay alive, and
+ * their options unchanged, until the server is drained. */
+typedef struct chem_server chem_server;
+
+typedef struct {
+  int64_t submitted, completed, cells_completed;
+  int64_t launches;
+  int64_t bytes_in_use, bytes_peak, budget_bytes;
+  int64_t queued;            /* waiting for admission */
+  int64_t in_flight;         /* admitted, not yet completed */
+} chem_server_stats;
+
+/* Create a server with an HBM budget for request state (bytes) and a number
+ * of concurrent launch streams (1..8).  The budget is reserved as one device
+ * arena at creation.  Errors: CHEM_ERR_ARG, CHEM_ERR_OOM, CHEM_ERR_DEVICE. */
+int chem_server_create(int64_t budget_bytes, int streams, chem_server** out);
+
+/* Queue one request: n_cells cells of mechanism m with host arrays T[n] and
+ * Y[S*n] (SoA, copied at submit), pressure p, step dt and tolerances.  *id
+ * receives the request id.  A request larger than the whole budget is
+ * rejected with CHEM_ERR_OOM. */
+int chem_server_submit(chem_server* s, chem_mech* m, int64_t n_cells, const double* T, const double* Y, double p,
+                       double dt, double rtol, double atol, int64_t* id);
+
+/* Non-blocking completion check.  Returns 1 and fills T_out/Y_out (host, may
+ * be NULL), latency_ms and status (CHEM_OK or CHEM_WARN_CELLS_FAILED) when the
+ * request is done (the request is then forgotten), 0 while pending, or an
+ * error code for an unknown id. */
+int chem_server_poll(chem_server* s, int64_t id, double* T_out, double* Y_out, double* latency_ms, int* status);
+
+/* Block until every submitted request has completed. */
+int chem_server_drain(chem_server* s);
+
+int chem_server_stats_get(chem_server* s, chem_server_stats* out);
+
+/* Stop the dispatcher and release everything (pending requests are
+ * dropped). */
+void chem_server_destroy(chem_server* s);
 
 /* Rates of one state per cell (Eq. 2-3, Eq. 7): wdot[S * n] (mol m^-3 s^-1,
  * required), f[(S+1) * n] (optional, the ODE right-hand side dY/dt, dT/dt)

@@ -16,7 +16,8 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unknown-warning-option",
 ]
-SOURCES = [os.path.join(CSRC, "chem_kernels.hip"), os.path.join(CSRC, "chem_host.cpp")]
+SOURCES = [os.path.join(CSRC, "chem_kernels.hip"), os.path.join(CSRC, "chem_host.cpp"),
+           os.path.join(CSRC, "chem_server.cpp")]
 
 
 def build(verbose: bool = False) -> str:
@@ -33,7 +34,7 @@ def build(verbose: bool = False) -> str:
         subprocess.run(cmd, check=True)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

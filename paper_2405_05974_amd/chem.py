@@ -36,8 +36,10 @@ OPT_WAVES_PER_CU = 8
 OPT_GROUP_WIDTH = 9
 
 EXPORTED = ("chem_mech_load", "chem_mech_load_str", "chem_mech_free", "chem_mech_info", "chem_set_stream",
-            "chem_set_option", "chem_integrate", "chem_integrate_ex", "chem_integrate_boxes", "chem_rates",
-            "chem_last_error")
+            "chem_set_option", "chem_integrate", "chem_integrate_ex", "chem_integrate_boxes", "chem_autotune",
+            "chem_rates",
+            "chem_last_error", "chem_server_create", "chem_server_submit", "chem_server_poll", "chem_server_drain",
+            "chem_server_stats_get", "chem_server_destroy")
 
 
 class ChemStats(C.Structure):
@@ -52,6 +54,14 @@ class ChemStats(C.Structure):
 
 class ChemBox(C.Structure):
     _fields_ = [("T", C.c_void_p), ("Y", C.c_void_p), ("n_cells", C.c_int64), ("dt", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("submitted", "completed", "cells_completed", "launches", "bytes_in_use",
+                                         "bytes_peak", "budget_bytes", "queued", "in_flight")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class ChemError(RuntimeError):
@@ -91,10 +101,20 @@ def load_library(path: Optional[str] = None):
                                       C.POINTER(ChemStats), i32p]
     lib.chem_integrate_boxes.argtypes = [vp, C.c_int, C.POINTER(ChemBox), C.c_double, C.c_double, C.c_double,
                                          C.POINTER(ChemStats), C.POINTER(C.c_double)]
+    lib.chem_autotune.argtypes = [vp, i64, dp, dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                  C.POINTER(C.c_int), C.POINTER(C.c_int)]
     lib.chem_rates.argtypes = [vp, i64, dp, dp, C.c_double, dp, dp, dp]
+    lib.chem_server_create.argtypes = [i64, C.c_int, C.POINTER(C.c_void_p)]
+    lib.chem_server_submit.argtypes = [vp, vp, i64, dp, dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                       C.POINTER(C.c_int64)]
+    lib.chem_server_poll.argtypes = [vp, i64, dp, dp, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    lib.chem_server_drain.argtypes = [vp]
+    lib.chem_server_stats_get.argtypes = [vp, C.POINTER(ServerStats)]
+    lib.chem_server_destroy.argtypes = [vp]
+    lib.chem_server_destroy.restype = None
     lib.chem_last_error.restype = C.c_char_p
     for name in EXPORTED:
-        if name not in ("chem_mech_free", "chem_last_error"):
+        if name not in ("chem_mech_free", "chem_last_error", "chem_server_destroy"):
             getattr(lib, name).restype = C.c_int
     if path is None:
         _lib = lib
@@ -188,6 +208,15 @@ class Mechanism:
         out["rc"] = rc
         return out
 
+    def autotune(self, T, Y, p: float, dt: float, rtol: float, atol: float, stream=None):
+        """Time the candidate launch shapes on a sample (unchanged) and keep the
+        fastest; returns (group_width, waves_per_cu)."""
+        _check(self.lib, self.lib.chem_set_stream(self.h, _stream_handle(stream)))
+        w, v = C.c_int(), C.c_int()
+        _check(self.lib, self.lib.chem_autotune(self.h, T.numel(), _ptr(T), _ptr(Y), float(p), float(dt),
+                                                float(rtol), float(atol), C.byref(w), C.byref(v)))
+        return w.value, v.value
+
     def integrate_boxes(self, boxes, p: float, rtol: float, atol: float, box_ms: bool = False, stream=None):
         """boxes: list of (T, Y, dt) with T [n_b] and Y [S, n_b] float64 CUDA
         tensors, updated in place.  Returns (stats dict, per-box completion
@@ -214,3 +243,62 @@ class Mechanism:
         _check(self.lib, self.lib.chem_set_stream(self.h, _stream_handle(stream)))
         _check(self.lib, self.lib.chem_rates(self.h, n, _ptr(T), _ptr(Y), float(p), _ptr(wdot), _ptr(f),
                                              _ptr(jac)))
+
+
+class Server:
+    """Continuous-batching request server (host arrays in, host arrays out)."""
+
+    def __init__(self, budget_bytes: int, streams: int = 4):
+        self.lib = load_library()
+        h = C.c_void_p()
+        _check(self.lib, self.lib.chem_server_create(int(budget_bytes), int(streams), C.byref(h)))
+        self.h = h
+        self._meta = {}
+
+    def submit(self, mech: "Mechanism", T, Y, p: float, dt: float, rtol: float, atol: float) -> int:
+        import numpy as np
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        Y = np.ascontiguousarray(Y, dtype=np.float64)
+        n = T.size
+        if Y.size != mech.S * n:
+            raise ValueError("Y must hold S * n values")
+        rid = C.c_int64()
+        _check(self.lib, self.lib.chem_server_submit(self.h, mech.h, n, T.ctypes.data, Y.ctypes.data, float(p),
+                                                     float(dt), float(rtol), float(atol), C.byref(rid)))
+        self._meta[rid.value] = (mech.S, n)
+        return rid.value
+
+    def poll(self, rid: int):
+        """None while pending, else (T, Y, latency_ms, status)."""
+        import numpy as np
+        S, n = self._meta[rid]
+        T = np.empty(n)
+        Y = np.empty((S, n))
+        lat = C.c_double()
+        status = C.c_int()
+        rc = _check(self.lib, self.lib.chem_server_poll(self.h, rid, T.ctypes.data if n else None,
+                                                        Y.ctypes.data if n else None, C.byref(lat),
+                                                        C.byref(status)))
+        if rc == 0:
+            return None
+        del self._meta[rid]
+        return T, Y, lat.value, status.value
+
+    def drain(self):
+        _check(self.lib, self.lib.chem_server_drain(self.h))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(self.lib, self.lib.chem_server_stats_get(self.h, C.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.chem_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,78 @@
+// chem_handle.h -- the library's mechanism handle (shared by the C-ABI
+// sources of libchem; not part of the public interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "chem_internal.h"
+
+namespace chemgpu {
+
+struct HostReaction {
+  int rev = 1, type = 0;
+  std::vector<int> reac, prod;
+  double A = 0, b = 0, Ea = 0;      // Ea in kcal/mol
+  double A0 = 0, b0 = 0, Ea0 = 0;
+};
+
+struct HostMech {
+  std::vector<double> emass;
+  std::vector<std::vector<int>> atoms;  // [S][E]
+  std::vector<double> W, a0, a1, hf, s0;
+  std::vector<HostReaction> rx;
+};
+
+}  // namespace chemgpu
+
+struct chem_mech {
+  chemgpu::HostMech host;
+  chemgpu::DevMech dev{};
+  void* blob = nullptr;          // device tables
+  const int* csr_off_np[3] = {nullptr, nullptr, nullptr};   // chunk offsets for 16/32/64 lanes per cell
+  int nch_np[3] = {0, 0, 0};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int n_cu = 256;
+  // options
+  int max_steps = 100000, q_max = 5, fixed_T = 0, fixed_step_n = 0, lu_fp32 = 0, ir_max = 3;
+  int use_graph = 1, waves_per_cu = 8;
+  // workspace
+  int32_t* rec = nullptr;
+  int64_t rec_cap = 0;
+  unsigned long long* dstats = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // batched boxes
+  chemgpu::BoxDev* dboxes = nullptr;
+  int* dremaining = nullptr;
+  int box_cap = 0;
+  chemgpu::BoxJob* djob = nullptr;
+  unsigned* dhead = nullptr;
+  int* host_done = nullptr;      // pinned, mapped
+  int* host_done_dev = nullptr;
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  const void* graph_key[4] = {nullptr, nullptr, nullptr, nullptr};
+  int graph_grid = 0, graph_np = 0, graph_f32 = -1;
+  chemgpu::IntParams graph_prm{};   // integration parameters baked into the captured launch
+};
+
+// Integration parameters from a handle's options (padding zeroed so that the
+// struct can be compared bytewise).
+inline chemgpu::IntParams make_int_params(const chem_mech* m, double p, double dt, double rtol, double atol) {
+  chemgpu::IntParams prm;
+  __builtin_memset(&prm, 0, sizeof prm);
+  prm.p = p;
+  prm.dt = dt;
+  prm.rtol = rtol;
+  prm.atol = atol;
+  prm.max_steps = m->max_steps;
+  prm.q_max = m->q_max;
+  prm.fixed_T = m->fixed_T;
+  prm.fixed_step_n = m->fixed_step_n;
+  prm.lu_fp32 = m->lu_fp32;
+  prm.ir_max = m->ir_max;
+  return prm;
+}

@@ -10,16 +10,21 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <map>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
 #include <vector>
 
+#include "chem_handle.h"
 #include "chem_internal.h"
 
 using chemgpu::DevMech;
 using chemgpu::IntParams;
 using chemgpu::RxParams;
+using chemgpu::HostMech;
+using chemgpu::HostReaction;
 
 namespace {
 
@@ -33,20 +38,6 @@ int fail(int code, const std::string& msg) {
 int hip_fail(hipError_t e, const char* where) {
   return fail(CHEM_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
-
-struct HostReaction {
-  int rev = 1, type = 0;
-  std::vector<int> reac, prod;
-  double A = 0, b = 0, Ea = 0;      // Ea in kcal/mol
-  double A0 = 0, b0 = 0, Ea0 = 0;
-};
-
-struct HostMech {
-  std::vector<double> emass;
-  std::vector<std::vector<int>> atoms;  // [S][E]
-  std::vector<double> W, a0, a1, hf, s0;
-  std::vector<HostReaction> rx;
-};
 
 // Whitespace tokenizer that drops '#' comments.
 class Tokens {
@@ -142,38 +133,6 @@ int parse_mechanism(const std::string& text, HostMech& m) {
 }
 
 }  // namespace
-
-struct chem_mech {
-  HostMech host;
-  DevMech dev{};
-  void* blob = nullptr;          // device tables
-  const int* csr_off_np[3] = {nullptr, nullptr, nullptr};   // chunk offsets for 16/32/64 lanes per cell
-  int nch_np[3] = {0, 0, 0};
-  hipStream_t stream = nullptr;
-  int device = 0;
-  int n_cu = 256;
-  // options
-  int max_steps = 100000, q_max = 5, fixed_T = 0, fixed_step_n = 0, lu_fp32 = 0, ir_max = 3;
-  int use_graph = 1, waves_per_cu = 8;
-  // workspace
-  int32_t* rec = nullptr;
-  int64_t rec_cap = 0;
-  unsigned long long* dstats = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  // batched boxes
-  chemgpu::BoxDev* dboxes = nullptr;
-  int* dremaining = nullptr;
-  int box_cap = 0;
-  chemgpu::BoxJob* djob = nullptr;
-  unsigned* dhead = nullptr;
-  int* host_done = nullptr;      // pinned, mapped
-  int* host_done_dev = nullptr;
-  hipStream_t capture_stream = nullptr;
-  hipGraphExec_t graph = nullptr;
-  const void* graph_key[4] = {nullptr, nullptr, nullptr, nullptr};
-  int graph_grid = 0, graph_np = 0, graph_f32 = -1;
-  IntParams graph_prm{};           // integration parameters baked into the captured launch
-};
 
 namespace {
 
@@ -681,6 +640,107 @@ int chem_integrate_boxes(chem_mech* m, int n_boxes, const chem_box* boxes, doubl
   } catch (...) {
     return fail(CHEM_ERR_OOM, "exception in chem_integrate_boxes");
   }
+}
+
+namespace {
+struct TuneKey {
+  int device, S, R;
+  bool operator<(const TuneKey& o) const {
+    return device != o.device ? device < o.device : (S != o.S ? S < o.S : R < o.R);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune_cache;
+
+int apply_tuning(chem_mech* m, int width, int waves) {
+  int rc = chem_set_option(m, CHEM_OPT_GROUP_WIDTH, width);
+  if (rc == CHEM_OK) rc = chem_set_option(m, CHEM_OPT_WAVES_PER_CU, waves);
+  return rc;
+}
+}  // namespace
+
+int chem_autotune(chem_mech* m, int64_t n_cells, const double* T, const double* Y, double p, double dt, double rtol,
+                  double atol, int* best_width, int* best_waves) {
+  if (!m) return fail(CHEM_ERR_ARG, "mechanism is NULL");
+  if (n_cells <= 0 || !T || !Y) return fail(CHEM_ERR_ARG, "autotune needs a non-empty sample");
+  const TuneKey key{m->device, m->dev.S, m->dev.R};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      if (best_width) *best_width = it->second.first;
+      if (best_waves) *best_waves = it->second.second;
+      return apply_tuning(m, it->second.first, it->second.second);
+    }
+  }
+  const int S = m->dev.S;
+  double* scratch = nullptr;
+  const size_t bytes = sizeof(double) * (size_t)(S + 1) * n_cells;
+  if (hipMalloc(&scratch, bytes) != hipSuccess) return fail(CHEM_ERR_OOM, "hipMalloc of autotune scratch");
+  const int64_t box = 4096;
+  std::vector<chem_box> boxes;
+  for (int64_t c0 = 0; c0 < n_cells; c0 += box) {
+    const int64_t nb = std::min(box, n_cells - c0);
+    boxes.push_back(chem_box{nullptr, nullptr, nb, dt});
+  }
+  // scratch layout: per box T[nb] then Y[S*nb]
+  {
+    int64_t off = 0;
+    for (auto& b : boxes) {
+      b.T = scratch + off;
+      b.Y = scratch + off + b.n_cells;
+      off += (S + 1) * b.n_cells;
+    }
+  }
+  const int old_width = m->dev.np_width, old_waves = m->waves_per_cu;
+  int best_w = old_width, best_v = old_waves;
+  double best_ms = 1e300;
+  int rc = CHEM_OK;
+  const int widths[3] = {16, 32, 64};
+  const int waves[4] = {4, 8, 12, 16};
+  for (int w : widths) {
+    if (w < m->dev.N) continue;
+    for (int v : waves) {
+      rc = apply_tuning(m, w, v);
+      if (rc != CHEM_OK) break;
+      // refresh the scratch copy of the sample (SoA per box)
+      int64_t c0 = 0;
+      hipError_t e = hipSuccess;
+      for (auto& b : boxes) {
+        e = hipMemcpyAsync(b.T, T + c0, sizeof(double) * b.n_cells, hipMemcpyDeviceToDevice, m->stream);
+        for (int k = 0; k < S && e == hipSuccess; ++k)
+          e = hipMemcpyAsync(b.Y + (int64_t)k * b.n_cells, Y + (int64_t)k * n_cells + c0,
+                             sizeof(double) * b.n_cells, hipMemcpyDeviceToDevice, m->stream);
+        c0 += b.n_cells;
+      }
+      if (e != hipSuccess) {
+        rc = hip_fail(e, "autotune copy");
+        break;
+      }
+      chem_stats st;
+      rc = chem_integrate_boxes(m, (int)boxes.size(), boxes.data(), p, rtol, atol, &st, nullptr);
+      if (rc < 0) break;
+      rc = CHEM_OK;
+      if (st.wall_ms < best_ms) {
+        best_ms = st.wall_ms;
+        best_w = w;
+        best_v = v;
+      }
+    }
+    if (rc != CHEM_OK) break;
+  }
+  (void)hipFree(scratch);
+  if (rc != CHEM_OK) {
+    (void)apply_tuning(m, old_width, old_waves);
+    return rc;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = {best_w, best_v};
+  }
+  if (best_width) *best_width = best_w;
+  if (best_waves) *best_waves = best_v;
+  return apply_tuning(m, best_w, best_v);
 }
 
 int chem_rates(chem_mech* m, int64_t n_cells, const double* T, const double* Y, double p, double* wdot, double* f,

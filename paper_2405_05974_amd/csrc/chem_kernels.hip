@@ -81,6 +81,24 @@ __device__ __forceinline__ double gsum(double v) {
   return v;
 }
 
+// Largest value over the group (NaN entries are ignored, as by fmax).
+template <int NP>
+__device__ __forceinline__ double gmax(double v) {
+  v = fmax(v, dpp_d<kRor8>(v));
+  v = fmax(v, dpp_d<kRor4>(v));
+  v = fmax(v, dpp_d<kRor2>(v));
+  v = fmax(v, dpp_d<kRor1>(v));
+  if constexpr (NP == 32) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const double a = fmax(readlane_d(v, 0), readlane_d(v, 16));
+    const double b = fmax(readlane_d(v, 32), readlane_d(v, 48));
+    v = lane < 32 ? a : b;
+  } else if constexpr (NP == 64) {
+    v = fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
+  }
+  return v;
+}
+
 template <int NP>
 __device__ __forceinline__ int gor(int v) {
   v |= dpp_i<kRor8>(v);
@@ -540,10 +558,18 @@ __device__ __forceinline__ double lu_solve(const Shared& sh, const double rdiag,
   return x;
 }
 
+// WRMS norm sqrt(sum (v w)^2 / N).  Cold cells can have right-hand sides
+// near 1e240 whose squares overflow: then the same norm is taken as
+// M sqrt(sum (v w / M)^2 / N) with M = max |v w| (M itself if not finite).
 template <int NP>
 __device__ __forceinline__ double wrms(const double v, const double w, const int N) {
   const double t = v * w;
-  return sqrt(gsum<NP>(t * t) / N);
+  const double s = gsum<NP>(t * t);
+  if (__builtin_expect(isfinite(s), 1)) return sqrt(s / N);
+  const double M = gmax<NP>(fabs(t));
+  if (!isfinite(M)) return M;
+  const double u = t / M;
+  return M * sqrt(gsum<NP>(u * u) / N);
 }
 
 // Mixed-precision option: the same pivoted factorisation of M = I - c J in
@@ -683,37 +709,6 @@ __device__ __forceinline__ void rescale(double (&D)[kQMax + 2], const int mdim, 
   }
 }
 
-// Mixture enthalpy sum_k Y_k H_k(T)/W_k of the group's cell (J/g).
-template <int NP>
-__device__ __forceinline__ double mix_enthalpy(const DevMech& m, const Spc& sc, const double Yr, const double T,
-                                               const int r) {
-  double v = 0.0;
-  if (r < m.S) {
-    const double Hk = sc.hf + kRu * (sc.a0 * (T - kTref) + sc.a1 * (T * T - kTref * kTref) * 0.5);
-    v = Yr * Hk / sc.W;
-  }
-  return gsum<NP>(v);
-}
-
-// Temperature at which the mixture with composition Y has enthalpy h: the
-// positive root of gamma T^2 + beta T + (alpha - h) = 0 in cancellation-free form.
-template <int NP>
-__device__ __forceinline__ double temperature_from_h(const DevMech& m, const Spc& sc, const double Yr, const double h,
-                                                     const int r) {
-  double al = 0.0, be = 0.0, ga = 0.0;
-  if (r < m.S) {
-    const double w = Yr / sc.W;
-    al = w * (sc.hf - kRu * sc.a0 * kTref - kRu * sc.a1 * kTref * kTref / 2.0);
-    be = w * kRu * sc.a0;
-    ga = w * kRu * sc.a1 / 2.0;
-  }
-  al = gsum<NP>(al);
-  be = gsum<NP>(be);
-  ga = gsum<NP>(ga);
-  const double c = h - al;
-  return 2.0 * c / (be + sqrt(be * be + 4.0 * ga * c));
-}
-
 __device__ __forceinline__ double pick(const double (&D)[kQMax + 2], const int j) {
   double v = 0.0;
 #pragma unroll
@@ -735,7 +730,8 @@ __device__ __forceinline__ void init_shared_constants(const DevMech& m, const Sh
 // the oracle's per-cell integrator (predictor/corrector in backward
 // differences, Newton with a fresh Jacobian and LU per attempt, WRMS error
 // test, quasi-constant step size with order selection after k+2 steps, and
-// enthalpy projection of T after every accepted step).
+// projection of the mass fractions onto Y >= 0 after every accepted step; T
+// follows its own equation and is not projected).
 // One group integrates cell `cell` of the SoA arrays (Tg, Yg, n) over [0, dt];
 // its record goes to column rec_cell of the rec array with rec_n columns.
 template <int NP, bool F32>
@@ -767,8 +763,6 @@ __device__ __forceinline__ void integrate_group(const DevMech& m, const IntParam
 #pragma unroll
     for (int j = 0; j < kQMax + 2; ++j) D[j] = 0.0;
     D[0] = (r < N) ? y0 : 0.0;
-    const double T0 = __shfl(y0, (lane - r) + S);
-    const double h0 = mix_enthalpy<NP>(m, sc, D[0], T0, r);
     double f, wdx;
     rhs_eval<NP, false>(m, sc, P.p, fixedT, D[0], f, wdx, sh);
     nrhs++;
@@ -889,9 +883,11 @@ __device__ __forceinline__ void integrate_group(const DevMech& m, const IntParam
         for (int j = kQMax; j >= 0; --j)
           if (j <= k) D[j] = D[j] + D[j + 1];
       }
-      if (!fixedT) {
-        const double Tn = temperature_from_h<NP>(m, sc, D[0], h0, rl);
-        if (rl == S) D[0] = Tn;
+      // positivity projection: a negative mass fraction is set to zero with
+      // all of its differences, so that the next predictor holds it there
+      if (rl < S && D[0] < 0.0) {
+#pragma unroll
+        for (int j = 0; j < kQMax + 2; ++j) D[j] = 0.0;
       }
       t = last ? dt : t + h;
       steps++;
@@ -990,10 +986,16 @@ __global__ __launch_bounds__(kWave) void boxes_kernel(const DevMech m, const Int
   const int nbox = job->n_boxes;
   const unsigned total = job->total_tiles;
   const int64_t rec_n = job->total_cells;
+  // The lane tests below use opaque_lane(), evaluated afresh in every
+  // iteration: with a lane test computed once before the loop, the compiler
+  // treats it as loop-invariant and may thread lane 0's two atomic regions
+  // into a loop of their own, leaving lanes 1..63 to re-enter the body
+  // without a new item.  The item is then taken from lane 0 by readlane,
+  // which does not depend on which lanes are active.
   for (;;) {
     unsigned item = 0;
-    if (lane == 0) item = atomicAdd(head, 1u);
-    item = (unsigned)__builtin_amdgcn_readfirstlane((int)item);
+    if (opaque_lane() == 0) item = atomicAdd(head, 1u);
+    item = (unsigned)__builtin_amdgcn_readlane((int)item, 0);
     if (item >= total) break;
     int lo = 0, hi = nbox - 1;
     while (lo < hi) {   // last box whose first tile is <= item
@@ -1004,7 +1006,7 @@ __global__ __launch_bounds__(kWave) void boxes_kernel(const DevMech m, const Int
     const BoxDev bx = boxes[lo];
     const int64_t c = ((int64_t)item - bx.tile_pre) * (kWave / NP) + g;
     if (c < bx.n) integrate_group<NP, F32>(m, P, bx.dt, sh, sc, bx.T, bx.Y, bx.n, c, rec, rec_n, bx.cell_off + c);
-    if (lane == 0) {
+    if (opaque_lane() == 0) {
       const int left = atomicSub(&remaining[lo], 1);
       if (left == 1 && host_done != nullptr) {
         __threadfence_system();
