@@ -60,6 +60,9 @@ def main():
                          "serve: Poisson request trace through the continuous-batching server; "
                          "copy: a plain device copy of known size (HBM counter calibration)")
     ap.add_argument("--lu-fp32", action="store_true", help="FP32 Newton-matrix LU with FP64 refinement")
+    ap.add_argument("--kernel", choices=["auto", "group", "lane"], default="auto",
+                    help="kernel family: lane = generated lane-per-cell kernels (S+1 <= 12), group = 16-64 lanes "
+                         "per cell; auto picks lane where it applies")
     ap.add_argument("--n-boxes", type=int, default=200)
     ap.add_argument("--max-box-cells", type=int, default=4096)
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: arrivals per second")
@@ -88,7 +91,8 @@ def main():
     n_tb = sum(r.kind == 1 for r in m.reactions)
     n_fo = sum(r.kind == 2 for r in m.reactions)
     gm = chem.Mechanism(m.to_text())
-    gm.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32))
+    gm.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32), kernel=KERNEL_CODES[args.kernel])
+    kname = kernel_name(args, m.n_species + 1)
     T0 = torch.tensor(w.T, dtype=torch.float64, device=dev)
     Y0 = torch.tensor(w.Y, dtype=torch.float64, device=dev)
     T = torch.empty_like(T0)
@@ -150,12 +154,24 @@ def main():
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-            "kernel": "integrate_kernel<16>", "kernel_ms": k_ms, "flops_per_launch": flops,
+            "kernel": kname, "kernel_ms": k_ms, "flops_per_launch": flops,
         },
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["accuracy"] = cpu_baseline(w, T, Y, args)
     print(json.dumps(out), flush=True)
+
+
+KERNEL_CODES = {"auto": 0, "group": 1, "lane": 2}
+LANE_MAX_N = 12          # largest S+1 the lane-per-cell kernels serve
+
+
+def kernel_name(args, N):
+    lane = args.kernel == "lane" or (args.kernel == "auto" and N <= LANE_MAX_N and not args.lu_fp32)
+    if lane:
+        return "chem_lpc_integrate (generated for the mechanism, hipRTC)"
+    np_ = 16 if N <= 16 else (32 if N <= 32 else 64)
+    return f"integrate_kernel<{np_}, {'true' if args.lu_fp32 else 'false'}>"
 
 
 def cpu_baseline(w, Tg, Yg, args):
@@ -200,7 +216,7 @@ def bench_boxes(args, torch, dev, chem, synth):
     m = synth.config_mechanism(4)
     boxes = synth.amr_boxes(m, args.n_boxes, synth.config_seed(4), max_cells=args.max_box_cells)
     gm = chem.Mechanism(m.to_text())
-    gm.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32))
+    gm.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32), kernel=KERNEL_CODES[args.kernel])
     src = [(torch.tensor(b.T, device=dev), torch.tensor(b.Y, device=dev), b.dt) for b in boxes]
     work = [(t.clone(), y.clone(), dt) for t, y, dt in src]
     sample_T = torch.cat([t[: min(256, t.numel())] for t, _, _ in src[:8]])
@@ -245,7 +261,8 @@ def bench_serve(args, torch, dev, chem, synth):
     mechs_ = [synth.config_mechanism(2), synth.config_mechanism(3)]
     handles = [chem.Mechanism(m.to_text()) for m in mechs_]
     for h in handles:
-        h.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32))
+        h.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32),
+                      kernel=KERNEL_CODES[args.kernel] if h.N <= LANE_MAX_N or args.kernel != "lane" else 0)
     arrivals = synth.poisson_trace(1005, args.rate, args.duration)
     rng = np.random.default_rng(1005)
     reqs = []

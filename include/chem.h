@@ -79,6 +79,9 @@ typedef struct {
 #define CHEM_OPT_GRAPH 7        /* 1: chem_integrate_boxes replays a captured hipGraph (default 1) */
 #define CHEM_OPT_WAVES_PER_CU 8 /* resident waves per CU for chem_integrate_boxes' persistent grid (1..32) */
 #define CHEM_OPT_GROUP_WIDTH 9  /* lanes per cell: 16, 32 or 64, at least S+1 (default: the smallest) */
+#define CHEM_OPT_KERNEL 10      /* kernel family: 0 auto (default), 1 group kernels (16-64 lanes per cell),
+                                   2 lane-per-cell kernels generated for the mechanism and compiled at run
+                                   time (S+1 <= 12, FP64 LU only; auto picks them where they apply) */
 
 /* Parse a mechanism from a file path / from text (format "chem-mech 1":
  * elements with masses; species with atom counts, inert flag and linear

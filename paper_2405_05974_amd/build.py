@@ -17,7 +17,7 @@ HIP_FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unknown-warning-option",
 ]
 SOURCES = [os.path.join(CSRC, "chem_kernels.hip"), os.path.join(CSRC, "chem_host.cpp"),
-           os.path.join(CSRC, "chem_server.cpp")]
+           os.path.join(CSRC, "chem_server.cpp"), os.path.join(CSRC, "chem_jit.cpp")]
 
 
 def build(verbose: bool = False) -> str:
@@ -34,7 +34,7 @@ def build(verbose: bool = False) -> str:
         subprocess.run(cmd, check=True)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lhiprtc", "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "chem_internal.h"
@@ -39,6 +41,13 @@ struct chem_mech {
   // options
   int max_steps = 100000, q_max = 5, fixed_T = 0, fixed_step_n = 0, lu_fp32 = 0, ir_max = 3;
   int use_graph = 1, waves_per_cu = 8;
+  int kernel_mode = 0;           // 0 auto, 1 group kernels, 2 lane-per-cell kernels
+  // lane-per-cell module (generated source, compiled on first use per device)
+  std::mutex lpc_mu;
+  std::string lpc_src;
+  void* lpc_integrate = nullptr;
+  void* lpc_boxes = nullptr;
+  int lpc_device = -1;
   // workspace
   int32_t* rec = nullptr;
   int64_t rec_cap = 0;
@@ -58,6 +67,22 @@ struct chem_mech {
   int graph_grid = 0, graph_np = 0, graph_f32 = -1;
   chemgpu::IntParams graph_prm{};   // integration parameters baked into the captured launch
 };
+
+namespace chemgpu {
+std::string lpc_source(const HostMech& m);
+int lpc_module(const std::string& src, int device, void** integrate_fn, void** boxes_fn, std::string& log);
+}  // namespace chemgpu
+
+// Kernel family for the next integration with this handle's options: sets
+// *lpc and, for the lane-per-cell family, compiles its module for the
+// handle's device on first use.  Returns a CHEM_* code.
+int chem_select_kernel(chem_mech* m, bool* lpc);
+// Cells per queue tile of the chosen family (64 for lane-per-cell).
+inline int chem_cells_per_tile(const chem_mech* m, bool lpc) { return lpc ? 64 : 64 / m->dev.np_width; }
+// Queue reset + persistent box kernel of the chosen family on `stream`.
+hipError_t chem_launch_box_queue(chem_mech* m, bool lpc, const chemgpu::IntParams& prm, const chemgpu::BoxDev* boxes,
+                                 const chemgpu::BoxJob* job, unsigned* head, int* remaining, int32_t* rec,
+                                 int* host_done, int grid, hipStream_t stream);
 
 // Integration parameters from a handle's options (padding zeroed so that the
 // struct can be compared bytewise).

@@ -312,6 +312,41 @@ int ensure_records(chem_mech* h, int64_t n) {
 
 }  // namespace
 
+// ------------------------------------------------ kernel family selection
+
+int chem_select_kernel(chem_mech* m, bool* lpc) {
+  const int N = m->dev.N;
+  bool want = false;
+  if (m->kernel_mode == 2) {
+    if (N > chemgpu::kLpcMaxN)
+      return fail(CHEM_ERR_UNSUPPORTED,
+                  "lane-per-cell kernels serve up to " + std::to_string(chemgpu::kLpcMaxN) + " state components");
+    if (m->lu_fp32) return fail(CHEM_ERR_UNSUPPORTED, "the FP32-LU option runs in the group kernels only");
+    want = true;
+  } else if (m->kernel_mode == 0) {
+    want = N <= chemgpu::kLpcMaxN && !m->lu_fp32;
+  }
+  *lpc = want;
+  if (!want) return CHEM_OK;
+  std::lock_guard<std::mutex> lk(m->lpc_mu);
+  if (m->lpc_integrate && m->lpc_device == m->device) return CHEM_OK;
+  if (m->lpc_src.empty()) m->lpc_src = chemgpu::lpc_source(m->host);
+  std::string log;
+  if (chemgpu::lpc_module(m->lpc_src, m->device, &m->lpc_integrate, &m->lpc_boxes, log) != 0)
+    return fail(CHEM_ERR_DEVICE, log);
+  m->lpc_device = m->device;
+  return CHEM_OK;
+}
+
+hipError_t chem_launch_box_queue(chem_mech* m, bool lpc, const chemgpu::IntParams& prm, const chemgpu::BoxDev* boxes,
+                                 const chemgpu::BoxJob* job, unsigned* head, int* remaining, int32_t* rec,
+                                 int* host_done, int grid, hipStream_t stream) {
+  if (!lpc) return chemgpu::launch_boxes(m->dev, prm, boxes, job, head, remaining, rec, host_done, grid, stream);
+  const hipError_t e = chemgpu::launch_boxes_init(boxes, job, head, remaining, stream);
+  if (e != hipSuccess) return e;
+  return chemgpu::launch_lpc_boxes(m->lpc_boxes, prm, boxes, job, head, remaining, rec, host_done, grid, stream);
+}
+
 extern "C" {
 
 int chem_mech_load_str(const char* text, chem_mech** out) {
@@ -401,6 +436,10 @@ int chem_set_option(chem_mech* m, int key, double value) {
       if (v < 1 || v > 32) return fail(CHEM_ERR_ARG, "waves_per_cu must be 1..32");
       m->waves_per_cu = (int)v;
       return CHEM_OK;
+    case CHEM_OPT_KERNEL:
+      if (v != 0 && v != 1 && v != 2) return fail(CHEM_ERR_ARG, "kernel must be 0 (auto), 1 (group) or 2 (lane per cell)");
+      m->kernel_mode = (int)v;
+      return CHEM_OK;
     case CHEM_OPT_GROUP_WIDTH: {
       const int wi = v == 16 ? 0 : (v == 32 ? 1 : (v == 64 ? 2 : -1));
       if (wi < 0 || v < m->dev.N) return fail(CHEM_ERR_ARG, "group width must be 16, 32 or 64 and at least S+1");
@@ -443,9 +482,13 @@ int chem_integrate_ex(chem_mech* m, int64_t n_cells, double* T, double* Y, doubl
   prm.fixed_step_n = m->fixed_step_n;
   prm.lu_fp32 = m->lu_fp32;
   prm.ir_max = m->ir_max;
+  bool lpc = false;
+  const int krc = chem_select_kernel(m, &lpc);
+  if (krc != CHEM_OK) return krc;
   hipError_t e = hipEventRecord(m->ev0, m->stream);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-  e = chemgpu::launch_integrate(m->dev, prm, T, Y, n_cells, rec, m->stream);
+  if (lpc) e = chemgpu::launch_lpc_integrate(m->lpc_integrate, prm, T, Y, n_cells, rec, m->stream);
+  else e = chemgpu::launch_integrate(m->dev, prm, T, Y, n_cells, rec, m->stream);
   if (e != hipSuccess) return hip_fail(e, "integrate kernel launch");
   e = hipEventRecord(m->ev1, m->stream);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -497,8 +540,8 @@ int ensure_boxes(chem_mech* m, int n_boxes) {
 }
 
 // Enqueue queue reset + persistent kernel (+ stats reduction) on `s`.
-hipError_t enqueue_boxes(chem_mech* m, const IntParams& prm, int grid, hipStream_t s) {
-  hipError_t e = chemgpu::launch_boxes(m->dev, prm, m->dboxes, m->djob, m->dhead, m->dremaining, m->rec,
+hipError_t enqueue_boxes(chem_mech* m, bool lpc, const IntParams& prm, int grid, hipStream_t s) {
+  hipError_t e = chem_launch_box_queue(m, lpc, prm, m->dboxes, m->djob, m->dhead, m->dremaining, m->rec,
                                        m->host_done_dev, grid, s);
   if (e != hipSuccess) return e;
   return chemgpu::launch_reduce_records_job(m->rec, m->djob, m->dstats, s);
@@ -527,7 +570,10 @@ int chem_integrate_boxes(chem_mech* m, int n_boxes, const chem_box* boxes, doubl
     for (int b = 0; b < n_boxes; ++b) order[b] = b;
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return boxes[a].n_cells > boxes[b].n_cells; });
-    const int cpw = 64 / m->dev.np_width;
+    bool lpc = false;
+    const int krc = chem_select_kernel(m, &lpc);
+    if (krc != CHEM_OK) return krc;
+    const int cpw = chem_cells_per_tile(m, lpc);
     std::vector<chemgpu::BoxDev> q(n_boxes);
     int64_t tiles = 0, cells = 0;
     for (int i = 0; i < n_boxes; ++i) {
@@ -577,7 +623,8 @@ int chem_integrate_boxes(chem_mech* m, int n_boxes, const chem_box* boxes, doubl
     if (m->use_graph) {
       const void* key[4] = {m->rec, m->dboxes, m->host_done_dev, m->blob};
       const bool stale = !m->graph || std::memcmp(key, m->graph_key, sizeof key) != 0 || m->graph_grid != grid ||
-                         m->graph_np != m->dev.np_width || m->graph_f32 != m->lu_fp32 || old_rec != m->rec ||
+                         m->graph_np != (lpc ? 1 : m->dev.np_width) || m->graph_f32 != m->lu_fp32 ||
+                         old_rec != m->rec ||
                          std::memcmp(&prm, &m->graph_prm, sizeof prm) != 0;
       if (stale) {
         if (m->graph) (void)hipGraphExecDestroy(m->graph);
@@ -585,7 +632,7 @@ int chem_integrate_boxes(chem_mech* m, int n_boxes, const chem_box* boxes, doubl
         hipGraph_t gr = nullptr;
         e = hipStreamBeginCapture(m->capture_stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-          const hipError_t le = enqueue_boxes(m, prm, grid, m->capture_stream);
+          const hipError_t le = enqueue_boxes(m, lpc, prm, grid, m->capture_stream);
           e = hipStreamEndCapture(m->capture_stream, &gr);
           if (le != hipSuccess) e = le;
         }
@@ -594,7 +641,7 @@ int chem_integrate_boxes(chem_mech* m, int n_boxes, const chem_box* boxes, doubl
         if (e != hipSuccess) return hip_fail(e, "hipGraph capture of the box launch");
         std::memcpy(m->graph_key, key, sizeof key);
         m->graph_grid = grid;
-        m->graph_np = m->dev.np_width;
+        m->graph_np = lpc ? 1 : m->dev.np_width;
         m->graph_f32 = m->lu_fp32;
         m->graph_prm = prm;
       }
@@ -602,7 +649,7 @@ int chem_integrate_boxes(chem_mech* m, int n_boxes, const chem_box* boxes, doubl
       // except the integration options baked into the capture
       e = hipGraphLaunch(m->graph, m->stream);
     } else {
-      e = enqueue_boxes(m, prm, grid, m->stream);
+      e = enqueue_boxes(m, lpc, prm, grid, m->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "box launch");
     e = hipEventRecord(m->ev1, m->stream);

@@ -83,5 +83,15 @@ hipError_t launch_reduce_records(const int32_t* rec, int64_t n, unsigned long lo
 hipError_t launch_reduce_records_job(const int32_t* rec, const BoxJob* job, unsigned long long* out,
                                      hipStream_t stream);
 size_t integrate_lds_bytes(int np_width, int N, bool f32);
+hipError_t launch_boxes_init(const BoxDev* boxes, const BoxJob* job, unsigned* head, int* remaining,
+                             hipStream_t stream);
+
+// Lane-per-cell kernels, generated per mechanism and compiled with hipRTC
+// (chem_jit.cpp).  Largest state size N = S + 1 they serve.
+constexpr int kLpcMaxN = 12;
+hipError_t launch_lpc_integrate(void* fn, const IntParams& prm, double* T, double* Y, int64_t n, int32_t* rec,
+                                hipStream_t stream);
+hipError_t launch_lpc_boxes(void* fn, const IntParams& prm, const BoxDev* boxes, const BoxJob* job, unsigned* head,
+                            int* remaining, int32_t* rec, int* host_done, int grid, hipStream_t stream);
 
 }  // namespace chemgpu

@@ -1,0 +1,343 @@
+// chem_jit.cpp -- mechanism-specific lane-per-cell kernels.
+//
+// The paper generates source code for each mechanism's production rates and
+// analytic Jacobian (Sec. 3.2) so that every species index and coefficient is
+// a constant the compiler can fold.  This file does the same at load time:
+// it writes HIP source for ch_eval<JAC> (rates of Eq. 2, production rates of
+// Eq. 3, the reactor right-hand side and its Jacobian, Eq. 7) with literal
+// indices and parameters, appends the lane-per-cell BDF integrator
+// (chem_lpc_body.inc), and compiles the result with hipRTC for the device's
+// architecture.  With all indices static the Newton matrix and its LU stay in
+// registers, one cell per lane, which suits mechanisms up to kLpcMaxN state
+// components.  Modules are cached per (device, source).
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <cinttypes>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "chem_handle.h"
+#include "chem_internal.h"
+
+namespace chemgpu {
+
+namespace {
+
+const char* kLpcBody =
+#include "chem_lpc_body.inc"
+    ;
+
+// exact double literal (hexadecimal floating point)
+std::string lit(double v) {
+  if (v == 0.0) return std::signbit(v) ? "(-0.0)" : "0.0";
+  char buf[64];
+  std::snprintf(buf, sizeof buf, "%a", v);
+  return std::string("(") + buf + ")";
+}
+
+std::string C(int k) { return "C[" + std::to_string(k) + "]"; }
+
+// product of the concentrations of `sp` except slot `skip` (-1: none)
+std::string product(const std::vector<int>& sp, int skip) {
+  std::string s;
+  for (size_t i = 0; i < sp.size(); ++i) {
+    if ((int)i == skip) continue;
+    s += s.empty() ? C(sp[i]) : " * " + C(sp[i]);
+  }
+  return s.empty() ? "1.0" : s;
+}
+
+void emit_nu_update(std::ostringstream& o, const char* arr, int k, int nu, const std::string& v) {
+  if (nu == 1) o << "    " << arr << "[" << k << "] += " << v << ";\n";
+  else if (nu == -1) o << "    " << arr << "[" << k << "] -= " << v << ";\n";
+  else o << "    " << arr << "[" << k << "] += " << lit((double)nu) << " * " << v << ";\n";
+}
+
+}  // namespace
+
+std::string lpc_source(const HostMech& m) {
+  const int S = (int)m.W.size(), R = (int)m.rx.size(), N = S + 1;
+  std::ostringstream o;
+  o << "// generated: lane-per-cell kernels for a mechanism with " << S << " species and " << R
+    << " reactions\n";
+  o << "#define CH_S " << S << "\n#define CH_N " << N << "\n";
+  o << "#define CH_RU " << lit(kRu) << "\n#define CH_RU_CGS " << lit(kRuCgs) << "\n#define CH_PATM " << lit(kPatm)
+    << "\n#define CH_TREF " << lit(kTref) << "\n";
+  // which species need a Gibbs energy
+  std::vector<char> needG(S, 0);
+  for (const HostReaction& x : m.rx)
+    if (x.rev) {
+      for (int k : x.reac) needG[k] = 1;
+      for (int k : x.prod) needG[k] = 1;
+    }
+  const double kcal_to_K = 4184.0 / kRu;
+  o << "template <bool JAC>\n__device__ __forceinline__ void ch_eval(const double (&y)[CH_N], const double p, "
+       "const int fixedT, double (&f)[CH_N], double (&J)[CH_N][CH_N]) {\n";
+  o << "  const double T = y[CH_S];\n  const double lnT = log(T);\n  const double invT = 1.0 / T;\n";
+  // divisions by constants are multiplications by their exact reciprocal
+  // literals; enthalpy and heat capacity are re-evaluated where they are used
+  // so that only the Jacobian keeps them across the reactions
+  auto Hk = [&](int k) {
+    return "(" + lit(m.hf[k]) + " + CH_RU * (" + lit(m.a0[k]) + " * (T - CH_TREF) + " + lit(m.a1[k]) +
+           " * (T * T - CH_TREF * CH_TREF) * 0.5))";
+  };
+  auto Cpk = [&](int k) { return "(CH_RU * (" + lit(m.a0[k]) + " + " + lit(m.a1[k]) + " * T))"; };
+  o << "  double sumYW = 0.0;\n";
+  for (int k = 0; k < S; ++k) o << "  sumYW += y[" << k << "] * " << lit(1.0 / m.W[k]) << ";\n";
+  o << "  const double Wbar = 1.0 / sumYW;\n";
+  o << "  const double rho = (p * 10.0) * Wbar / (CH_RU_CGS * T);\n";
+  o << "  const double irho = 1.0 / rho;\n";
+  o << "  double C[CH_S];\n  double Mc = 0.0;\n";
+  for (int k = 0; k < S; ++k) o << "  C[" << k << "] = rho * y[" << k << "] * " << lit(1.0 / m.W[k]) << ";\n";
+  for (int k = 0; k < S; ++k) o << "  Mc += C[" << k << "];\n";
+  o << "  const double lnTr = log(T * " << lit(1.0 / kTref) << ");\n";
+  o << "  const double invRT = 1.0 / (CH_RU * T);\n";
+  o << "  const double lnc0 = log(CH_PATM * invRT * 1.0e-6);\n";
+  o << "  double H[CH_S], G[CH_S];\n";
+  o << "  if (JAC) {\n";
+  for (int k = 0; k < S; ++k) o << "    H[" << k << "] = " << Hk(k) << ";\n";
+  o << "  }\n";
+  for (int k = 0; k < S; ++k) {
+    if (needG[k])
+      o << "  G[" << k << "] = (" << Hk(k) << " - T * (" << lit(m.s0[k]) << " + CH_RU * (" << lit(m.a0[k])
+        << " * lnTr + " << lit(m.a1[k]) << " * (T - CH_TREF)))) * invRT;\n";
+    else
+      o << "  G[" << k << "] = 0.0;\n";
+  }
+  o << "  (void)lnc0; (void)invRT; (void)lnT; (void)Mc;\n";
+  o << "  double wd[CH_S];\n";
+  // For JAC the species block of J first accumulates A = d wdot / dC at fixed
+  // T (without the [M] rank-one part, kept in ak) and is turned into the
+  // (Y, T) Jacobian in place at the end.
+  o << "  double bT[CH_S], ak[CH_S];\n";
+  o << "#pragma unroll\n  for (int k = 0; k < CH_S; ++k) {\n    wd[k] = 0.0;\n    bT[k] = 0.0;\n    ak[k] = 0.0;\n"
+       "    if (JAC) {\n#pragma unroll\n      for (int c = 0; c < CH_S; ++c) J[k][c] = 0.0;\n    }\n  }\n";
+  for (int j = 0; j < R; ++j) {
+    const HostReaction& x = m.rx[j];
+    std::vector<int> nu(S, 0);
+    for (int k : x.reac) nu[k] -= 1;
+    for (int k : x.prod) nu[k] += 1;
+    const int dnu = (int)x.prod.size() - (int)x.reac.size();
+    o << "  {  // reaction " << j << "\n";
+    o << "    const double kinf = exp(" << lit(std::log(x.A)) << " + " << lit(x.b) << " * lnT - "
+      << lit(x.Ea * kcal_to_K) << " * invT);\n";
+    o << "    double kf = kinf;\n";
+    o << "    double dlnkf = (" << lit(x.b) << " + " << lit(x.Ea * kcal_to_K) << " * invT) * invT;\n";
+    o << "    double dkfdM = 0.0;\n    (void)dlnkf; (void)dkfdM;\n";
+    if (x.type == 2) {
+      o << "    const double k0 = exp(" << lit(std::log(x.A0)) << " + " << lit(x.b0) << " * lnT - "
+        << lit(x.Ea0 * kcal_to_K) << " * invT);\n";
+      o << "    const double dlnk0 = (" << lit(x.b0) << " + " << lit(x.Ea0 * kcal_to_K) << " * invT) * invT;\n";
+      o << "    const double Pr = k0 * Mc / kinf;\n";
+      o << "    kf = kinf * Pr / (1.0 + Pr);\n";
+      o << "    dlnkf = dlnkf + (dlnk0 - dlnkf) / (1.0 + Pr);\n";
+      o << "    dkfdM = k0 / ((1.0 + Pr) * (1.0 + Pr));\n";
+      o << "    (void)dlnk0;\n";
+    }
+    o << "    const double pf = " << product(x.reac, -1) << ";\n";
+    o << "    const double pr = " << product(x.prod, -1) << ";\n";
+    o << "    double kr = 0.0, dkr = 0.0, dkrdM = 0.0;\n    (void)dkr; (void)dkrdM;\n";
+    if (x.rev) {
+      // sum_k nu_k G_k / RT and sum_k nu_k H_k over the net stoichiometry
+      std::string sg, shh;
+      for (int k = 0; k < S; ++k) {
+        if (!nu[k]) continue;
+        const std::string term = (nu[k] == 1 || nu[k] == -1) ? "" : lit((double)std::abs(nu[k])) + " * ";
+        const char* sign = nu[k] > 0 ? (sg.empty() ? "" : " + ") : (sg.empty() ? "-" : " - ");
+        sg += sign + term + "G[" + std::to_string(k) + "]";
+        shh += sign + term + "H[" + std::to_string(k) + "]";
+      }
+      if (sg.empty()) {
+        sg = "0.0";
+        shh = "0.0";
+      }
+      o << "    const double ratio = exp((" << sg << ") - " << lit((double)dnu) << " * lnc0);\n";
+      o << "    kr = kf * ratio;\n";
+      o << "    if (JAC) {\n";
+      o << "      const double dlnKc = (" << shh << ") * invRT * invT - " << lit((double)dnu) << " * invT;\n";
+      o << "      dkr = kr * (dlnkf - dlnKc);\n";
+      o << "      dkrdM = dkfdM * ratio;\n    }\n";
+    }
+    o << "    const double mf = " << (x.type == 1 ? "Mc" : "1.0") << ";\n";
+    o << "    const double net = kf * pf - kr * pr;\n";
+    o << "    const double Q = mf * net;\n";
+    for (int k = 0; k < S; ++k)
+      if (nu[k]) emit_nu_update(o, "wd", k, nu[k], "Q");
+    o << "    if (JAC) {\n";
+    o << "      const double dQdT = mf * (kf * dlnkf * pf - dkr * pr);\n";
+    for (int k = 0; k < S; ++k)
+      if (nu[k]) emit_nu_update(o, "  bT", k, nu[k], "dQdT");
+    if (x.type == 1 || x.type == 2) {
+      o << "      const double q0 = " << (x.type == 1 ? "net" : "dkfdM * pf - dkrdM * pr") << ";\n";
+      for (int k = 0; k < S; ++k)
+        if (nu[k]) emit_nu_update(o, "  ak", k, nu[k], "q0");
+    }
+    for (size_t s = 0; s < x.reac.size(); ++s) {
+      o << "      {\n        const double dq = mf * kf * " << product(x.reac, (int)s) << ";\n";
+      for (int k = 0; k < S; ++k)
+        if (nu[k]) emit_nu_update(o, ("    J[" + std::to_string(k) + "]").c_str(), x.reac[s], nu[k], "dq");
+      o << "      }\n";
+    }
+    for (size_t s = 0; s < x.prod.size(); ++s) {
+      o << "      {\n        const double dq = -mf * kr * " << product(x.prod, (int)s) << ";\n";
+      for (int k = 0; k < S; ++k)
+        if (nu[k]) emit_nu_update(o, ("    J[" + std::to_string(k) + "]").c_str(), x.prod[s], nu[k], "dq");
+      o << "      }\n";
+    }
+    o << "    }\n  }\n";
+  }
+  // right-hand side
+  o << "  double num = 0.0, den = 0.0;\n";
+  for (int k = 0; k < S; ++k) {
+    o << "  num += (JAC ? H[" << k << "] : " << Hk(k) << ") * wd[" << k << "];\n";
+    o << "  den += C[" << k << "] * " << Cpk(k) << ";\n";
+  }
+  o << "  const double iden = 1.0 / den;\n";
+  for (int k = 0; k < S; ++k) o << "  f[" << k << "] = " << lit(m.W[k]) << " * wd[" << k << "] * irho;\n";
+  o << "  f[CH_S] = fixedT ? 0.0 : -num * iden;\n";
+  // Jacobian: row sums AC_k = sum_c A_kc C_c and the temperature row (which
+  // needs the column sums sum_k H_k A_kc) from A, then the species rows in place
+  o << "  if (JAC) {\n";
+  o << "    double AC[CH_S], dwdT[CH_S];\n";
+  o << "#pragma unroll\n    for (int k = 0; k < CH_S; ++k) {\n      double s = 0.0;\n"
+       "#pragma unroll\n      for (int c = 0; c < CH_S; ++c) s += (J[k][c] + ak[k]) * C[c];\n"
+       "      AC[k] = s;\n      dwdT[k] = bT[k] - s * invT;\n    }\n";
+  o << "    double iW[CH_S], Wk[CH_S], Cp[CH_S];\n";
+  for (int k = 0; k < S; ++k) o << "    Cp[" << k << "] = " << Cpk(k) << ";\n";
+  for (int k = 0; k < S; ++k) o << "    iW[" << k << "] = " << lit(1.0 / m.W[k]) << ";\n";
+  for (int k = 0; k < S; ++k) o << "    Wk[" << k << "] = " << lit(m.W[k]) << ";\n";
+  o << "    if (fixedT) {\n#pragma unroll\n      for (int c = 0; c < CH_N; ++c) J[CH_S][c] = 0.0;\n    } else {\n";
+  o << "      double HAC = 0.0, HdwdT = 0.0, Cpw = 0.0, Ca1 = 0.0;\n";
+  o << "#pragma unroll\n      for (int k = 0; k < CH_S; ++k) {\n        HAC += H[k] * AC[k];\n"
+       "        HdwdT += H[k] * dwdT[k];\n        Cpw += Cp[k] * wd[k];\n      }\n";
+  for (int k = 0; k < S; ++k) o << "      Ca1 += C[" << k << "] * CH_RU * " << lit(m.a1[k]) << ";\n";
+  o << "#pragma unroll\n      for (int c = 0; c < CH_S; ++c) {\n        double colsum = 0.0;\n"
+       "#pragma unroll\n        for (int k = 0; k < CH_S; ++k) colsum += H[k] * (J[k][c] + ak[k]);\n"
+       "        const double dN = (rho * iW[c]) * colsum - (Wbar * iW[c]) * HAC;\n"
+       "        const double dD = (rho * Cp[c] - Wbar * den) * iW[c];\n"
+       "        J[CH_S][c] = -dN * iden + num * dD * (iden * iden);\n      }\n";
+  o << "      const double dN = Cpw + HdwdT;\n      const double dD = -den * invT + Ca1;\n"
+       "      J[CH_S][CH_S] = -dN * iden + num * dD * (iden * iden);\n    }\n";
+  o << "#pragma unroll\n    for (int k = 0; k < CH_S; ++k) {\n"
+       "      const double fac = Wk[k] * irho;\n      const double fw = Wk[k] * wd[k] * irho;\n"
+       "#pragma unroll\n      for (int c = 0; c < CH_S; ++c)\n"
+       "        J[k][c] = fac * ((J[k][c] + ak[k]) * rho * iW[c] - Wbar * iW[c] * AC[k]) + fw * Wbar * iW[c];\n"
+       "      J[k][CH_S] = fac * dwdT[k] + fw * invT;\n    }\n";
+  o << "  }\n}\n";
+  o << kLpcBody;
+  return o.str();
+}
+
+namespace {
+
+struct LpcModule {
+  hipModule_t mod = nullptr;
+  hipFunction_t integrate = nullptr;
+  hipFunction_t boxes = nullptr;
+};
+
+std::mutex g_jit_mu;
+std::map<std::pair<int, std::string>, LpcModule> g_jit_cache;   // (device, source)
+
+}  // namespace
+
+// Compile (or fetch) the lane-per-cell module of `src` for the current device.
+int lpc_module(const std::string& src, int device, void** integrate_fn, void** boxes_fn, std::string& log) {
+  std::lock_guard<std::mutex> lk(g_jit_mu);
+  auto key = std::make_pair(device, src);
+  auto it = g_jit_cache.find(key);
+  if (it != g_jit_cache.end()) {
+    *integrate_fn = it->second.integrate;
+    *boxes_fn = it->second.boxes;
+    return 0;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    log = "hipGetDeviceProperties failed";
+    return -1;
+  }
+  std::string arch = prop.gcnArchName;
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch = arch.substr(0, colon);
+  hiprtcProgram prog;
+  if (hiprtcCreateProgram(&prog, src.c_str(), "chem_lpc.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS) {
+    log = "hiprtcCreateProgram failed";
+    return -1;
+  }
+  const std::string off = "--offload-arch=" + arch;
+  const char* opts[] = {off.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+  const hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+  size_t log_size = 0;
+  hiprtcGetProgramLogSize(prog, &log_size);
+  if (log_size > 1) {
+    log.resize(log_size);
+    hiprtcGetProgramLog(prog, &log[0]);
+  }
+  if (rc != HIPRTC_SUCCESS) {
+    hiprtcDestroyProgram(&prog);
+    log = "hipRTC compile of the lane-per-cell kernels failed: " + log;
+    return -1;
+  }
+  size_t code_size = 0;
+  hiprtcGetCodeSize(prog, &code_size);
+  std::vector<char> code(code_size);
+  hiprtcGetCode(prog, code.data());
+  hiprtcDestroyProgram(&prog);
+  LpcModule mod;
+  if (hipModuleLoadData(&mod.mod, code.data()) != hipSuccess ||
+      hipModuleGetFunction(&mod.integrate, mod.mod, "chem_lpc_integrate") != hipSuccess ||
+      hipModuleGetFunction(&mod.boxes, mod.mod, "chem_lpc_boxes") != hipSuccess) {
+    log = "loading the lane-per-cell module failed";
+    return -1;
+  }
+  g_jit_cache[key] = mod;
+  *integrate_fn = mod.integrate;
+  *boxes_fn = mod.boxes;
+  return 0;
+}
+
+namespace {
+struct LpcParams {   // layout of ChParams in the generated source
+  double p, dt, rtol, atol;
+  int max_steps, q_max, fixed_T, fixed_step_n;
+};
+LpcParams lpc_params(const IntParams& prm) {
+  LpcParams q;
+  q.p = prm.p;
+  q.dt = prm.dt;
+  q.rtol = prm.rtol;
+  q.atol = prm.atol;
+  q.max_steps = prm.max_steps;
+  q.q_max = prm.q_max;
+  q.fixed_T = prm.fixed_T;
+  q.fixed_step_n = prm.fixed_step_n;
+  return q;
+}
+}  // namespace
+
+hipError_t launch_lpc_integrate(void* fn, const IntParams& prm, double* T, double* Y, int64_t n, int32_t* rec,
+                                hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  LpcParams q = lpc_params(prm);
+  long long nn = n;
+  void* args[] = {&T, &Y, &nn, &rec, &q};
+  const unsigned blocks = (unsigned)((n + 63) / 64);
+  return hipModuleLaunchKernel((hipFunction_t)fn, blocks, 1, 1, 64, 1, 1, 0, stream, args, nullptr);
+}
+
+hipError_t launch_lpc_boxes(void* fn, const IntParams& prm, const BoxDev* boxes, const BoxJob* job, unsigned* head,
+                            int* remaining, int32_t* rec, int* host_done, int grid, hipStream_t stream) {
+  LpcParams q = lpc_params(prm);
+  void* args[] = {&q, &boxes, &job, &head, &remaining, &rec, &host_done};
+  return hipModuleLaunchKernel((hipFunction_t)fn, (unsigned)grid, 1, 1, 64, 1, 1, 0, stream, args, nullptr);
+}
+
+}  // namespace chemgpu

@@ -1152,6 +1152,12 @@ hipError_t launch_boxes_np(const DevMech& m, const IntParams& prm, const BoxDev*
 
 }  // namespace
 
+hipError_t launch_boxes_init(const BoxDev* boxes, const BoxJob* job, unsigned* head, int* remaining,
+                             hipStream_t stream) {
+  hipLaunchKernelGGL(boxes_init_kernel, dim3(64), dim3(256), 0, stream, boxes, job, head, remaining);
+  return hipGetLastError();
+}
+
 hipError_t launch_boxes(const DevMech& m, const IntParams& prm, const BoxDev* boxes, const BoxJob* job,
                         unsigned* head, int* remaining, int32_t* rec, int* host_done, int grid,
                         hipStream_t stream) {

@@ -166,7 +166,9 @@ bool ensure_slot(Slot& sl, int nbox, int64_t cells) {
 bool launch_group(chem_server* s, Slot& sl, const std::vector<Request*>& group) {
   chem_mech* m = group[0]->m;
   const int S = m->dev.S;
-  const int cpw = 64 / m->dev.np_width;
+  bool lpc = false;
+  if (chem_select_kernel(m, &lpc) != CHEM_OK) return false;
+  const int cpw = chem_cells_per_tile(m, lpc);
   int64_t cells = 0;
   for (Request* r : group) cells += r->n;
   if (!ensure_slot(sl, (int)group.size(), cells)) return false;
@@ -208,7 +210,7 @@ bool launch_group(chem_server* s, Slot& sl, const std::vector<Request*>& group) 
     return false;
   const chemgpu::IntParams prm = make_int_params(m, group[0]->p, 0.0, group[0]->rtol, group[0]->atol);
   const int grid = (int)std::min<int64_t>(tiles, (int64_t)m->waves_per_cu * s->n_cu);
-  if (chemgpu::launch_boxes(m->dev, prm, sl.dboxes, sl.djob, sl.dhead, sl.dremaining, sl.rec, nullptr, grid, st) !=
+  if (chem_launch_box_queue(m, lpc, prm, sl.dboxes, sl.djob, sl.dhead, sl.dremaining, sl.rec, nullptr, grid, st) !=
       hipSuccess)
     return false;
   for (size_t i = 0; i < group.size(); ++i) {
