@@ -65,12 +65,26 @@ void emit_nu_update(std::ostringstream& o, const char* arr, int k, int nu, const
 
 std::string lpc_source(const HostMech& m) {
   const int S = (int)m.W.size(), R = (int)m.rx.size(), N = S + 1;
+  // Mechanism parameters are read from a __constant__ table (scalar loads,
+  // several constants per instruction) rather than written as literals, each
+  // of which costs two scalar moves wherever it is used.
+  std::vector<double> pool;
+  std::map<unsigned long long, int> pool_idx;
+  auto kc = [&](double v) {
+    unsigned long long bits;
+    std::memcpy(&bits, &v, sizeof bits);
+    auto it = pool_idx.find(bits);
+    int idx;
+    if (it != pool_idx.end()) {
+      idx = it->second;
+    } else {
+      idx = (int)pool.size();
+      pool.push_back(v);
+      pool_idx[bits] = idx;
+    }
+    return "K[" + std::to_string(idx) + "]";
+  };
   std::ostringstream o;
-  o << "// generated: lane-per-cell kernels for a mechanism with " << S << " species and " << R
-    << " reactions\n";
-  o << "#define CH_S " << S << "\n#define CH_N " << N << "\n";
-  o << "#define CH_RU " << lit(kRu) << "\n#define CH_RU_CGS " << lit(kRuCgs) << "\n#define CH_PATM " << lit(kPatm)
-    << "\n#define CH_TREF " << lit(kTref) << "\n";
   // which species need a Gibbs energy
   std::vector<char> needG(S, 0);
   for (const HostReaction& x : m.rx)
@@ -81,24 +95,25 @@ std::string lpc_source(const HostMech& m) {
   const double kcal_to_K = 4184.0 / kRu;
   o << "template <bool JAC>\n__device__ __forceinline__ void ch_eval(const double (&y)[CH_N], const double p, "
        "const int fixedT, double (&f)[CH_N], double (&J)[CH_N][CH_N]) {\n";
+  o << "  const double* __restrict__ K = ch_K;\n";
   o << "  const double T = y[CH_S];\n  const double lnT = log(T);\n  const double invT = 1.0 / T;\n";
-  // divisions by constants are multiplications by their exact reciprocal
-  // literals; enthalpy and heat capacity are re-evaluated where they are used
+  // divisions by constants are multiplications by their exact reciprocals;
+  // enthalpy and heat capacity are re-evaluated where they are used
   // so that only the Jacobian keeps them across the reactions
   auto Hk = [&](int k) {
-    return "(" + lit(m.hf[k]) + " + CH_RU * (" + lit(m.a0[k]) + " * (T - CH_TREF) + " + lit(m.a1[k]) +
+    return "(" + kc(m.hf[k]) + " + CH_RU * (" + kc(m.a0[k]) + " * (T - CH_TREF) + " + kc(m.a1[k]) +
            " * (T * T - CH_TREF * CH_TREF) * 0.5))";
   };
-  auto Cpk = [&](int k) { return "(CH_RU * (" + lit(m.a0[k]) + " + " + lit(m.a1[k]) + " * T))"; };
+  auto Cpk = [&](int k) { return "(CH_RU * (" + kc(m.a0[k]) + " + " + kc(m.a1[k]) + " * T))"; };
   o << "  double sumYW = 0.0;\n";
-  for (int k = 0; k < S; ++k) o << "  sumYW += y[" << k << "] * " << lit(1.0 / m.W[k]) << ";\n";
+  for (int k = 0; k < S; ++k) o << "  sumYW += y[" << k << "] * " << kc(1.0 / m.W[k]) << ";\n";
   o << "  const double Wbar = 1.0 / sumYW;\n";
   o << "  const double rho = (p * 10.0) * Wbar / (CH_RU_CGS * T);\n";
   o << "  const double irho = 1.0 / rho;\n";
   o << "  double C[CH_S];\n  double Mc = 0.0;\n";
-  for (int k = 0; k < S; ++k) o << "  C[" << k << "] = rho * y[" << k << "] * " << lit(1.0 / m.W[k]) << ";\n";
+  for (int k = 0; k < S; ++k) o << "  C[" << k << "] = rho * y[" << k << "] * " << kc(1.0 / m.W[k]) << ";\n";
   for (int k = 0; k < S; ++k) o << "  Mc += C[" << k << "];\n";
-  o << "  const double lnTr = log(T * " << lit(1.0 / kTref) << ");\n";
+  o << "  const double lnTr = log(T * " << kc(1.0 / kTref) << ");\n";
   o << "  const double invRT = 1.0 / (CH_RU * T);\n";
   o << "  const double lnc0 = log(CH_PATM * invRT * 1.0e-6);\n";
   o << "  double H[CH_S], G[CH_S];\n";
@@ -107,8 +122,8 @@ std::string lpc_source(const HostMech& m) {
   o << "  }\n";
   for (int k = 0; k < S; ++k) {
     if (needG[k])
-      o << "  G[" << k << "] = (" << Hk(k) << " - T * (" << lit(m.s0[k]) << " + CH_RU * (" << lit(m.a0[k])
-        << " * lnTr + " << lit(m.a1[k]) << " * (T - CH_TREF)))) * invRT;\n";
+      o << "  G[" << k << "] = (" << Hk(k) << " - T * (" << kc(m.s0[k]) << " + CH_RU * (" << kc(m.a0[k])
+        << " * lnTr + " << kc(m.a1[k]) << " * (T - CH_TREF)))) * invRT;\n";
     else
       o << "  G[" << k << "] = 0.0;\n";
   }
@@ -127,15 +142,15 @@ std::string lpc_source(const HostMech& m) {
     for (int k : x.prod) nu[k] += 1;
     const int dnu = (int)x.prod.size() - (int)x.reac.size();
     o << "  {  // reaction " << j << "\n";
-    o << "    const double kinf = exp(" << lit(std::log(x.A)) << " + " << lit(x.b) << " * lnT - "
-      << lit(x.Ea * kcal_to_K) << " * invT);\n";
+    o << "    const double kinf = exp(" << kc(std::log(x.A)) << " + " << kc(x.b) << " * lnT - "
+      << kc(x.Ea * kcal_to_K) << " * invT);\n";
     o << "    double kf = kinf;\n";
-    o << "    double dlnkf = (" << lit(x.b) << " + " << lit(x.Ea * kcal_to_K) << " * invT) * invT;\n";
+    o << "    double dlnkf = (" << kc(x.b) << " + " << kc(x.Ea * kcal_to_K) << " * invT) * invT;\n";
     o << "    double dkfdM = 0.0;\n    (void)dlnkf; (void)dkfdM;\n";
     if (x.type == 2) {
-      o << "    const double k0 = exp(" << lit(std::log(x.A0)) << " + " << lit(x.b0) << " * lnT - "
-        << lit(x.Ea0 * kcal_to_K) << " * invT);\n";
-      o << "    const double dlnk0 = (" << lit(x.b0) << " + " << lit(x.Ea0 * kcal_to_K) << " * invT) * invT;\n";
+      o << "    const double k0 = exp(" << kc(std::log(x.A0)) << " + " << kc(x.b0) << " * lnT - "
+        << kc(x.Ea0 * kcal_to_K) << " * invT);\n";
+      o << "    const double dlnk0 = (" << kc(x.b0) << " + " << kc(x.Ea0 * kcal_to_K) << " * invT) * invT;\n";
       o << "    const double Pr = k0 * Mc / kinf;\n";
       o << "    kf = kinf * Pr / (1.0 + Pr);\n";
       o << "    dlnkf = dlnkf + (dlnk0 - dlnkf) / (1.0 + Pr);\n";
@@ -201,7 +216,7 @@ std::string lpc_source(const HostMech& m) {
     o << "  den += C[" << k << "] * " << Cpk(k) << ";\n";
   }
   o << "  const double iden = 1.0 / den;\n";
-  for (int k = 0; k < S; ++k) o << "  f[" << k << "] = " << lit(m.W[k]) << " * wd[" << k << "] * irho;\n";
+  for (int k = 0; k < S; ++k) o << "  f[" << k << "] = " << kc(m.W[k]) << " * wd[" << k << "] * irho;\n";
   o << "  f[CH_S] = fixedT ? 0.0 : -num * iden;\n";
   // Jacobian: row sums AC_k = sum_c A_kc C_c and the temperature row (which
   // needs the column sums sum_k H_k A_kc) from A, then the species rows in place
@@ -212,13 +227,13 @@ std::string lpc_source(const HostMech& m) {
        "      AC[k] = s;\n      dwdT[k] = bT[k] - s * invT;\n    }\n";
   o << "    double iW[CH_S], Wk[CH_S], Cp[CH_S];\n";
   for (int k = 0; k < S; ++k) o << "    Cp[" << k << "] = " << Cpk(k) << ";\n";
-  for (int k = 0; k < S; ++k) o << "    iW[" << k << "] = " << lit(1.0 / m.W[k]) << ";\n";
-  for (int k = 0; k < S; ++k) o << "    Wk[" << k << "] = " << lit(m.W[k]) << ";\n";
+  for (int k = 0; k < S; ++k) o << "    iW[" << k << "] = " << kc(1.0 / m.W[k]) << ";\n";
+  for (int k = 0; k < S; ++k) o << "    Wk[" << k << "] = " << kc(m.W[k]) << ";\n";
   o << "    if (fixedT) {\n#pragma unroll\n      for (int c = 0; c < CH_N; ++c) J[CH_S][c] = 0.0;\n    } else {\n";
   o << "      double HAC = 0.0, HdwdT = 0.0, Cpw = 0.0, Ca1 = 0.0;\n";
   o << "#pragma unroll\n      for (int k = 0; k < CH_S; ++k) {\n        HAC += H[k] * AC[k];\n"
        "        HdwdT += H[k] * dwdT[k];\n        Cpw += Cp[k] * wd[k];\n      }\n";
-  for (int k = 0; k < S; ++k) o << "      Ca1 += C[" << k << "] * CH_RU * " << lit(m.a1[k]) << ";\n";
+  for (int k = 0; k < S; ++k) o << "      Ca1 += C[" << k << "] * CH_RU * " << kc(m.a1[k]) << ";\n";
   o << "#pragma unroll\n      for (int c = 0; c < CH_S; ++c) {\n        double colsum = 0.0;\n"
        "#pragma unroll\n        for (int k = 0; k < CH_S; ++k) colsum += H[k] * (J[k][c] + ak[k]);\n"
        "        const double dN = (rho * iW[c]) * colsum - (Wbar * iW[c]) * HAC;\n"
@@ -232,8 +247,17 @@ std::string lpc_source(const HostMech& m) {
        "        J[k][c] = fac * ((J[k][c] + ak[k]) * rho * iW[c] - Wbar * iW[c] * AC[k]) + fw * Wbar * iW[c];\n"
        "      J[k][CH_S] = fac * dwdT[k] + fw * invT;\n    }\n";
   o << "  }\n}\n";
-  o << kLpcBody;
-  return o.str();
+  std::ostringstream head;
+  head << "// generated: lane-per-cell kernels for a mechanism with " << S << " species and " << R
+       << " reactions\n";
+  head << "#define CH_S " << S << "\n#define CH_N " << N << "\n";
+  head << "#define CH_RU " << lit(kRu) << "\n#define CH_RU_CGS " << lit(kRuCgs) << "\n#define CH_PATM "
+       << lit(kPatm) << "\n#define CH_TREF " << lit(kTref) << "\n";
+  head << "__constant__ double ch_K[" << std::max<size_t>(pool.size(), 1) << "] = {";
+  for (size_t i = 0; i < pool.size(); ++i) head << (i ? ", " : "") << lit(pool[i]);
+  if (pool.empty()) head << "0.0";
+  head << "};\n";
+  return head.str() + o.str() + kLpcBody;
 }
 
 namespace {
