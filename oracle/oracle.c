@@ -25,7 +25,8 @@
  *   - species thermo with linear heat capacity cp/R = a0 + a1 T.
  *   - quasi-constant-step BDF in backward-difference form, orders 1-5, a
  *     fresh Jacobian and LU every step, WRMS error control, and after every
- *     accepted step projection of Y onto Y >= 0.
+ *     accepted step projection of Y onto Y >= 0 (steps that would leave a
+ *     mass fraction below -atol are rejected).
  * Units: the interface is SI (K, Pa, s, mass fractions); concentrations and
  * rate constants are cgs (mol/cm^3, A in mol-cm-s units).
  *
@@ -557,12 +558,16 @@ static void orc_rescale(int n, double **D, int mdim, double r) {
  * An error test failure shrinks h by max(0.2, 0.9 e^(-1/(k+1))); three in a
  * row drop to order 1 with h /= 10.  When t + 1.1 h reaches dt the step is set
  * to end exactly at dt.  Every change of h rescales the
- * differences D_1..D_{min(k+1,q_max)}.  After every accepted step, a mass
- * fraction that came out negative is set to zero together with all of its
- * backward differences (projection onto Y >= 0, Sandu 2001: with reverse rate
- * constants as large as these, a species left below zero drives reactions
- * that share it on both sides backwards and the solution runs away; the reset
- * differences make the next predictor hold it at zero).  T is integrated
+ * differences D_1..D_{min(k+1,q_max)}.  A converged corrector that leaves a
+ * mass fraction below -atol is rejected like a failed error test (h /= 4; an
+ * inequality constraint Y >= -atol in CVODE's manner): the higher BDF orders
+ * can extrapolate a decaying species below zero, and accepting that sets up
+ * a cycle of overshoot and Newton failure at the scale of atol.  After every
+ * accepted step a mass fraction still below zero is set to zero together
+ * with all of its backward differences (projection onto Y >= 0, Sandu 2001:
+ * with reverse rate constants as large as these, a species left below zero
+ * drives reactions that share it on both sides backwards and the solution
+ * runs away; the reset differences make the next predictor hold it at zero).  T is integrated
  * through its own equation and is not projected: moving T after a step moves
  * the fast partial equilibria with it, and the next step then sees a jump no
  * step size above the round-off floor can resolve.  The mixture enthalpy is
@@ -656,6 +661,20 @@ static void orc_integrate_cell(const orc_mech *m, double *y, double p, double dt
       h *= 0.25;
       nk = 0;
       continue;
+    }
+    /* inequality constraint: a corrector with a mass fraction below -atol is
+     * rejected like a failed error test (h /= 4) */
+    if (!fixed) {
+      int viol = 0;
+      for (int i = 0; i < S; ++i)
+        if (pred[i] + d[i] < -atol) viol = 1;
+      if (viol) {
+        st->n_etf++;
+        orc_rescale(N, D, k + 1 <= q_max ? k + 1 : q_max, 0.25);
+        h *= 0.25;
+        nk = 0;
+        continue;
+      }
     }
     double err = orc_wrms(N, d, w) / (k + 1);
     if (!fixed && !(err <= 1.0)) {
