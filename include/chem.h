@@ -112,8 +112,9 @@ int chem_set_option(chem_mech* m, int key, double value);
 /* Integrate n_cells reactors in place over [0, dt] at pressure p.
  * T[n_cells] and Y[S * n_cells] (device, SoA) are read and overwritten with
  * the state at dt.  rtol > 0, atol >= 0 set the WRMS error weights
- * 1/(rtol |y| + atol) used for every component, T included.  A mass
- * fraction that a step leaves negative is set to zero (outputs are >= 0);
+ * 1/(rtol |y| + atol) used for every component, T included.  Steps that
+ * would leave a mass fraction below -atol are rejected, and one left
+ * negative is set to zero (outputs are >= 0);
  * T follows its own equation, so the mixture enthalpy is conserved to the
  * integration tolerance.  stats (host
  * pointer, may be NULL) receives the totals.  Returns CHEM_OK,

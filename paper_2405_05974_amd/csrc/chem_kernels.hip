@@ -730,8 +730,9 @@ __device__ __forceinline__ void init_shared_constants(const DevMech& m, const Sh
 // the oracle's per-cell integrator (predictor/corrector in backward
 // differences, Newton with a fresh Jacobian and LU per attempt, WRMS error
 // test, quasi-constant step size with order selection after k+2 steps, and
-// projection of the mass fractions onto Y >= 0 after every accepted step; T
-// follows its own equation and is not projected).
+// rejection of steps that leave a mass fraction below -atol, projection of
+// the mass fractions onto Y >= 0 after every accepted step; T follows its
+// own equation).
 // One group integrates cell `cell` of the SoA arrays (Tg, Yg, n) over [0, dt];
 // its record goes to column rec_cell of the rec array with rec_n columns.
 template <int NP, bool F32>
@@ -848,6 +849,15 @@ __device__ __forceinline__ void integrate_group(const DevMech& m, const IntParam
       }
       if (!conv && !fixed) {
         nnnf++;
+        rescale(D, k + 1 <= q_max ? k + 1 : q_max, 0.25);
+        h *= 0.25;
+        nk = 0;
+        continue;
+      }
+      // inequality constraint: a corrector with a mass fraction below -atol is
+      // rejected like a failed error test
+      if (!fixed && gor<NP>((rl < S && pred + d < -P.atol) ? 1 : 0)) {
+        netf++;
         rescale(D, k + 1 <= q_max ? k + 1 : q_max, 0.25);
         h *= 0.25;
         nk = 0;
