@@ -117,44 +117,18 @@ __device__ __forceinline__ int gor(int v) {
   return v;
 }
 
-// (v, idx) takes (ov, oi) if that is larger, ties to the lower index.
-__device__ __forceinline__ void take_best(double& v, int& idx, double ov, int oi) {
-  if (ov > v || (ov == v && oi < idx)) {
-    v = ov;
-    idx = oi;
-  }
-}
-
-template <int CTRL>
-__device__ __forceinline__ void argmax_step(double& v, int& idx) {
-  const double ov = dpp_d<CTRL>(v);
-  const int oi = dpp_i<CTRL>(idx);
-  take_best(v, idx, ov, oi);
-}
-
-// Largest value over the group, ties to the lowest lane index.
+// Pivot of a column: the group lane holding the largest candidate, ties to
+// the lowest lane.  A max reduction gives the value; a ballot of the lanes
+// that hold it gives the lowest such lane as a bit index, without carrying
+// (value, index) pairs through the reduction.  Candidates must not be NaN.
 template <int NP>
-__device__ __forceinline__ void gargmax(double& v, int& idx) {
-  argmax_step<kRor8>(v, idx);
-  argmax_step<kRor4>(v, idx);
-  argmax_step<kRor2>(v, idx);
-  argmax_step<kRor1>(v, idx);
-  if constexpr (NP >= 32) {
-    double v0 = readlane_d(v, 0), v1 = readlane_d(v, 16), v2 = readlane_d(v, 32), v3 = readlane_d(v, 48);
-    int i0 = __builtin_amdgcn_readlane(idx, 0), i1 = __builtin_amdgcn_readlane(idx, 16);
-    int i2 = __builtin_amdgcn_readlane(idx, 32), i3 = __builtin_amdgcn_readlane(idx, 48);
-    take_best(v0, i0, v1, i1);
-    take_best(v2, i2, v3, i3);
-    if constexpr (NP == 32) {
-      const int lane = threadIdx.x & (kWave - 1);
-      v = lane < 32 ? v0 : v2;
-      idx = lane < 32 ? i0 : i2;
-    } else {
-      take_best(v0, i0, v2, i2);
-      v = v0;
-      idx = i0;
-    }
-  }
+__device__ __forceinline__ int gpivot(const double cand) {
+  const double mx = gmax<NP>(cand);
+  const unsigned long long hit = __ballot(cand == mx);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int base = lane - lane % NP;
+  const unsigned long long mine = (NP == kWave) ? hit : ((hit >> base) & ((1ull << (NP & 63)) - 1ull));
+  return __builtin_ctzll(mine);
 }
 
 // Value of group lane k (a compile-time constant after unrolling) to every
@@ -507,8 +481,7 @@ __device__ __forceinline__ void factor_newton_matrix(const Shared& sh, const dou
   for (int k = 0; k < NP; ++k) {
     double cand = used ? -1.0 : fabs(a[k]);
     if (!(cand == cand)) cand = -1.0;
-    int idx = r;
-    gargmax<NP>(cand, idx);
+    const int idx = gpivot<NP>(cand);
     double* prow = sh.prow + (k & 1) * kWave + base;
     if (r == idx) {
       used = true;
@@ -591,8 +564,7 @@ __device__ __forceinline__ void factor_newton_matrix_f32(const Shared& sh, const
   for (int k = 0; k < NP; ++k) {
     double cand = used ? -1.0 : (double)fabsf(a[k]);
     if (!(cand == cand)) cand = -1.0;
-    int idx = r;
-    gargmax<NP>(cand, idx);
+    const int idx = gpivot<NP>(cand);
     float* prow = sh.prow32 + (k & 1) * kWave + base;
     if (r == idx) {
       used = true;
