@@ -95,7 +95,13 @@ std::string lpc_source(const HostMech& m) {
   const double kcal_to_K = 4184.0 / kRu;
   o << "template <bool JAC>\n__device__ __forceinline__ void ch_eval(const double (&y)[CH_N], const double p, "
        "const int fixedT, double (&f)[CH_N], double (&J)[CH_N][CH_N]) {\n";
-  o << "  const double* __restrict__ K = ch_K;\n";
+  // K reads the table through the constant address space, so loads stay scalar.  At the top
+  // and before each reaction the pointer passes through an empty asm statement: the compiler
+  // can no longer hoist every table load out of the step loop (about 130 doubles kept live in
+  // scalar registers and spilled), and loads each reaction's constants from the scalar cache
+  // where they are used.
+  o << "  typedef const __attribute__((address_space(4))) double* ch_kptr;\n";
+  o << "  ch_kptr __restrict__ K = (ch_kptr)ch_K;\n  asm volatile(\"\" : \"+s\"(K));\n";
   o << "  const double T = y[CH_S];\n  const double lnT = log(T);\n  const double invT = 1.0 / T;\n";
   // divisions by constants are multiplications by their exact reciprocals;
   // enthalpy and heat capacity are re-evaluated where they are used
@@ -141,7 +147,7 @@ std::string lpc_source(const HostMech& m) {
     for (int k : x.reac) nu[k] -= 1;
     for (int k : x.prod) nu[k] += 1;
     const int dnu = (int)x.prod.size() - (int)x.reac.size();
-    o << "  {  // reaction " << j << "\n";
+    o << "  asm volatile(\"\" : \"+s\"(K));\n  {  // reaction " << j << "\n";
     o << "    const double kinf = exp(" << kc(std::log(x.A)) << " + " << kc(x.b) << " * lnT - "
       << kc(x.Ea * kcal_to_K) << " * invT);\n";
     o << "    double kf = kinf;\n";
