@@ -193,7 +193,7 @@ __device__ __forceinline__ float gbcastf(float v, const int k) {
 // wave lane, per-species vectors by group base + species index, and each
 // group owns NP matrix rows of NP+1 doubles.
 struct Shared {
-  double* J;      // [groups][NP][ldj]: Jacobian rows, then the pivot-ordered LU factors
+  double* J;      // [groups][rows][ldj]: Jacobian rows, then the pivot-ordered LU factors
   double* C;      // [64] concentrations (mol/cm^3)
   double* G;      // [64] G_k/(R T)
   double* H;      // [64] H_k, J/mol
@@ -203,14 +203,16 @@ struct Shared {
   double* rq;     // [9][64]: Q, dQ/dT, q0, dQ/dC slots 0..5
   double* prow;   // [2][64] pivot row, double-buffered
   int* perm;      // [64] lane whose row holds pivot k
-  float* F;       // [groups][NP][ldj] FP32 LU factors (mixed-precision option only)
+  float* F;       // [groups][rows][ldj] FP32 LU factors (mixed-precision option only)
   float* prow32;  // [2][64] FP32 pivot row
   int ldj;
+  int rows;       // stored matrix rows per group: N; rows N..NP-1 are identity and not stored
 };
 
-__device__ __forceinline__ Shared carve(double* smem, int NP, bool f32 = false) {
+__device__ __forceinline__ Shared carve(double* smem, int NP, int N, bool f32 = false) {
   Shared s;
   s.ldj = NP + 1;
+  s.rows = N;
   s.C = smem;
   s.G = s.C + kWave;
   s.H = s.G + kWave;
@@ -221,7 +223,7 @@ __device__ __forceinline__ Shared carve(double* smem, int NP, bool f32 = false) 
   s.prow = s.rq + 9 * kWave;
   s.perm = reinterpret_cast<int*>(s.prow + 2 * kWave);
   s.J = s.prow + 2 * kWave + kWave / 2;   // perm takes 64 ints = 32 doubles
-  const size_t jd = (size_t)(kWave / NP) * NP * (NP + 1);
+  const size_t jd = (size_t)(kWave / NP) * N * (NP + 1);
   s.F = f32 ? reinterpret_cast<float*>(s.J + jd) : nullptr;
   s.prow32 = f32 ? s.F + jd : nullptr;
   return s;
@@ -230,9 +232,8 @@ __device__ __forceinline__ Shared carve(double* smem, int NP, bool f32 = false) 
 }  // namespace
 
 size_t integrate_lds_bytes(int np_width, int N, bool f32) {
-  (void)N;
   const int groups = kWave / np_width;
-  const size_t jd = (size_t)groups * np_width * (np_width + 1);
+  const size_t jd = (size_t)groups * N * (np_width + 1);
   const size_t doubles = 6 * kWave + 9 * kWave + 2 * kWave + kWave / 2 + jd;
   return doubles * sizeof(double) + (f32 ? (jd + 2 * kWave) * sizeof(float) : 0);
 }
@@ -258,7 +259,7 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
   const int base = g * NP;
   const int S = m.S;
   const bool isSp = r < S;
-  double* Jg = sh.J + (size_t)g * NP * sh.ldj;
+  double* Jg = sh.J + (size_t)g * sh.rows * sh.ldj;
 
   const double T = __shfl(yr, base + S);
   const double lnT = log(T);
@@ -281,7 +282,7 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
   sh.C[lane] = C;
   sh.G[lane] = Gd;
   sh.H[lane] = H;
-  if (JAC) {
+  if (JAC && r < sh.rows) {
 #pragma unroll
     for (int c = 0; c < NP; ++c) Jg[r * sh.ldj + c] = 0.0;
   }
@@ -471,10 +472,10 @@ __device__ __forceinline__ void factor_newton_matrix(const Shared& sh, const dou
   const int lane = opaque_lane();
   const int r = lane % NP;
   const int base = lane - r;
-  double* Jg = sh.J + (size_t)(lane / NP) * NP * sh.ldj;
+  double* Jg = sh.J + (size_t)(lane / NP) * sh.rows * sh.ldj;
   double a[NP];
 #pragma unroll
-  for (int c = 0; c < NP; ++c) a[c] = ((c == r) ? 1.0 : 0.0) - cfac * Jg[r * sh.ldj + c];
+  for (int c = 0; c < NP; ++c) a[c] = ((c == r) ? 1.0 : 0.0) - (r < sh.rows ? cfac * Jg[r * sh.ldj + c] : 0.0);
   bool used = false;
   int pos = -1;
 #pragma unroll
@@ -498,13 +499,16 @@ __device__ __forceinline__ void factor_newton_matrix(const Shared& sh, const dou
       for (int c = k + 1; c < NP; ++c) a[c] -= l * prow[c];
     }
   }
-  // store the rows in pivot order (every lane pivots exactly once)
-  if (pos >= 0) {
+  // store the rows in pivot order (every lane pivots exactly once).  The
+  // identity rows of lanes r >= N pivot at their own position k = r (their
+  // column k < N entries are zero and stay zero), so positions >= N are the
+  // identity and are not stored.
+  if (pos >= 0 && pos < sh.rows) {
 #pragma unroll
     for (int c = 0; c < NP; ++c) Jg[pos * sh.ldj + c] = a[c];
   }
   wave_sync();
-  rdiag = 1.0 / Jg[r * sh.ldj + r];
+  rdiag = r < sh.rows ? 1.0 / Jg[r * sh.ldj + r] : 1.0;
 }
 
 // Solve M x = b with the pivot-ordered factors; lane r holds b_r (component
@@ -514,18 +518,18 @@ __device__ __forceinline__ double lu_solve(const Shared& sh, const double rdiag,
   const int lane = opaque_lane();
   const int r = lane % NP;
   const int base = lane - r;
-  const double* Jg = sh.J + (size_t)(lane / NP) * NP * sh.ldj;
+  const double* Jg = sh.J + (size_t)(lane / NP) * sh.rows * sh.ldj;
   double z = __shfl(b, base + sh.perm[base + r]);   // b in pivot order
 #pragma unroll
   for (int k = 0; k < NP - 1; ++k) {
     const double zk = gbcast<NP>(z, k);
-    if (r > k) z -= Jg[r * sh.ldj + k] * zk;
+    if (r > k && r < sh.rows) z -= Jg[r * sh.ldj + k] * zk;
   }
   double x = 0.0;
 #pragma unroll
   for (int k = NP - 1; k >= 0; --k) {
     const double xk = gbcast<NP>(z * rdiag, k);
-    if (r < k) z -= Jg[r * sh.ldj + k] * xk;
+    if (r < k && r < sh.rows) z -= Jg[r * sh.ldj + k] * xk;
     if (r == k) x = xk;
   }
   return x;
@@ -553,11 +557,12 @@ __device__ __forceinline__ void factor_newton_matrix_f32(const Shared& sh, const
   const int lane = opaque_lane();
   const int r = lane % NP;
   const int base = lane - r;
-  const double* Jg = sh.J + (size_t)(lane / NP) * NP * sh.ldj;
-  float* Fg = sh.F + (size_t)(lane / NP) * NP * sh.ldj;
+  const double* Jg = sh.J + (size_t)(lane / NP) * sh.rows * sh.ldj;
+  float* Fg = sh.F + (size_t)(lane / NP) * sh.rows * sh.ldj;
   float a[NP];
 #pragma unroll
-  for (int c = 0; c < NP; ++c) a[c] = (float)(((c == r) ? 1.0 : 0.0) - cfac * Jg[r * sh.ldj + c]);
+  for (int c = 0; c < NP; ++c)
+    a[c] = (float)(((c == r) ? 1.0 : 0.0) - (r < sh.rows ? cfac * Jg[r * sh.ldj + c] : 0.0));
   bool used = false;
   int pos = -1;
 #pragma unroll
@@ -581,12 +586,12 @@ __device__ __forceinline__ void factor_newton_matrix_f32(const Shared& sh, const
       for (int c = k + 1; c < NP; ++c) a[c] -= l * prow[c];
     }
   }
-  if (pos >= 0) {
+  if (pos >= 0 && pos < sh.rows) {
 #pragma unroll
     for (int c = 0; c < NP; ++c) Fg[pos * sh.ldj + c] = a[c];
   }
   wave_sync();
-  rdiag = 1.0f / Fg[r * sh.ldj + r];
+  rdiag = r < sh.rows ? 1.0f / Fg[r * sh.ldj + r] : 1.0f;
 }
 
 template <int NP>
@@ -594,18 +599,18 @@ __device__ __forceinline__ double lu_solve_f32(const Shared& sh, const float rdi
   const int lane = opaque_lane();
   const int r = lane % NP;
   const int base = lane - r;
-  const float* Fg = sh.F + (size_t)(lane / NP) * NP * sh.ldj;
+  const float* Fg = sh.F + (size_t)(lane / NP) * sh.rows * sh.ldj;
   float z = (float)__shfl(b, base + sh.perm[base + r]);
 #pragma unroll
   for (int k = 0; k < NP - 1; ++k) {
     const float zk = gbcastf<NP>(z, k);
-    if (r > k) z -= Fg[r * sh.ldj + k] * zk;
+    if (r > k && r < sh.rows) z -= Fg[r * sh.ldj + k] * zk;
   }
   float x = 0.0f;
 #pragma unroll
   for (int k = NP - 1; k >= 0; --k) {
     const float xk = gbcastf<NP>(z * rdiag, k);
-    if (r < k) z -= Fg[r * sh.ldj + k] * xk;
+    if (r < k && r < sh.rows) z -= Fg[r * sh.ldj + k] * xk;
     if (r == k) x = xk;
   }
   return (double)x;
@@ -620,12 +625,12 @@ __device__ __forceinline__ double solve_refined(const Shared& sh, const float rd
                                                 const double w, const int N, const int ir_max, int& sweeps) {
   const int lane = opaque_lane();
   const int r = lane % NP;
-  const double* Jg = sh.J + (size_t)(lane / NP) * NP * sh.ldj;
+  const double* Jg = sh.J + (size_t)(lane / NP) * sh.rows * sh.ldj;
   double x = lu_solve_f32<NP>(sh, rdiag, b);
   for (int s = 0; s < ir_max; ++s) {
     double jx = 0.0;
 #pragma unroll
-    for (int c = 0; c < NP; ++c) jx += Jg[r * sh.ldj + c] * gbcast<NP>(x, c);
+    for (int c = 0; c < NP; ++c) jx += (r < sh.rows ? Jg[r * sh.ldj + c] : 0.0) * gbcast<NP>(x, c);
     const double res = b - (x - cfac * jx);
     const double dx = lu_solve_f32<NP>(sh, rdiag, res);
     x += dx;
@@ -938,7 +943,7 @@ __global__ __launch_bounds__(kWave) void integrate_kernel(const DevMech m, const
                                                           double* __restrict__ Yg, const int64_t n,
                                                           int32_t* __restrict__ rec) {
   extern __shared__ double smem[];
-  const Shared sh = carve(smem, NP, F32);
+  const Shared sh = carve(smem, NP, m.N, F32);
   const int lane = threadIdx.x & (kWave - 1);
   const int r = lane % NP;
   const int64_t cell = (int64_t)blockIdx.x * (kWave / NP) + lane / NP;
@@ -959,7 +964,7 @@ __global__ __launch_bounds__(kWave) void boxes_kernel(const DevMech m, const Int
                                                       unsigned* __restrict__ head, int* __restrict__ remaining,
                                                       int32_t* __restrict__ rec, int* __restrict__ host_done) {
   extern __shared__ double smem[];
-  const Shared sh = carve(smem, NP, F32);
+  const Shared sh = carve(smem, NP, m.N, F32);
   const int lane = threadIdx.x & (kWave - 1);
   const int r = lane % NP;
   const int g = lane / NP;
@@ -1015,7 +1020,7 @@ __global__ __launch_bounds__(kWave) void rates_kernel(const DevMech m, const dou
                                                       const int64_t n, double* __restrict__ wdot,
                                                       double* __restrict__ fout, double* __restrict__ jac) {
   extern __shared__ double smem[];
-  const Shared sh = carve(smem, NP);
+  const Shared sh = carve(smem, NP, m.N);
   const int lane = threadIdx.x & (kWave - 1);
   const int r = lane % NP;
   const int g = lane / NP;
@@ -1033,7 +1038,7 @@ __global__ __launch_bounds__(kWave) void rates_kernel(const DevMech m, const dou
   if (r < S) wdot[(int64_t)r * n + cell] = wd * 1.0e6;   // mol/(cm^3 s) -> mol/(m^3 s)
   if (fout != nullptr && r < N) fout[(int64_t)r * n + cell] = f;
   if (jac != nullptr && r < N) {
-    const double* Jg = sh.J + (size_t)g * NP * sh.ldj;
+    const double* Jg = sh.J + (size_t)g * sh.rows * sh.ldj;
     for (int c = 0; c < N; ++c) jac[((int64_t)r * N + c) * n + cell] = Jg[r * sh.ldj + c];
   }
 }
