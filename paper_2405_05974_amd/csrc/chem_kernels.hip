@@ -191,7 +191,8 @@ __device__ __forceinline__ float gbcastf(float v, const int k) {
 
 // LDS carve-up for one wave (64/NP groups).  Reaction scratch is indexed by
 // wave lane, per-species vectors by group base + species index, and each
-// group owns NP matrix rows of NP+1 doubles.
+// group owns N matrix rows of NP+1 doubles (rows N..NP-1 of the padded
+// matrix are identity and are not stored).
 struct Shared {
   double* J;      // [groups][rows][ldj]: Jacobian rows, then the pivot-ordered LU factors
   double* C;      // [64] concentrations (mol/cm^3)
