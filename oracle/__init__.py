@@ -32,7 +32,7 @@ def build(extra_flags=()) -> str:
 
 class OrcOpts(C.Structure):
     _fields_ = [("max_steps", C.c_int), ("q_max", C.c_int), ("fixed_T", C.c_int),
-                ("fixed_step_n", C.c_int)]
+                ("fixed_step_n", C.c_int), ("jac_mode", C.c_int)]
 
 
 class OrcCellStats(C.Structure):
@@ -64,6 +64,8 @@ def _load(path: Optional[str] = None):
     lib.orc_rates.argtypes = [C.c_void_p, C.c_double, dp, C.c_double, dp, dp, dp, dp]
     lib.orc_rhs.argtypes = [C.c_void_p, dp, C.c_double, C.c_int, dp]
     lib.orc_jac.argtypes = [C.c_void_p, dp, C.c_double, C.c_int, dp]
+    lib.orc_jac_fd.argtypes = [C.c_void_p, dp, C.c_double, C.c_int, dp, C.c_double, dp]
+    lib.orc_jac_fd.restype = C.c_int
     lib.orc_lu.argtypes = [C.c_int, dp, ip]
     lib.orc_lu.restype = C.c_int
     lib.orc_lu_solve.argtypes = [C.c_int, dp, ip, dp]
@@ -146,6 +148,15 @@ class Mech:
         self.lib.orc_jac(self.h, _dp(y), float(p), int(fixed_T), _dp(J))
         return J.reshape(self.N, self.N)
 
+    def jac_fd(self, y: np.ndarray, p: float, w: np.ndarray, h: float, fixed_T: bool = False) -> np.ndarray:
+        """The one-sided difference-quotient Jacobian (increment rule of the
+        integrator's finite-difference mode) at y, with error weights w and step h."""
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        J = np.zeros(self.N * self.N)
+        self.lib.orc_jac_fd(self.h, _dp(y), float(p), int(fixed_T), _dp(w), float(h), _dp(J))
+        return J.reshape(self.N, self.N)
+
     def enthalpy(self, T: float, Y: np.ndarray) -> float:
         Y = np.ascontiguousarray(Y, dtype=np.float64)
         return self.lib.orc_enthalpy(self.h, float(T), _dp(Y))
@@ -157,14 +168,14 @@ class Mech:
     # -- whole-batch integration ---------------------------------------------
     def integrate(self, T: np.ndarray, Y: np.ndarray, p: float, dt: float, rtol: float, atol: float,
                   max_steps: int = 100000, q_max: int = 5, fixed_T: bool = False, fixed_step_n: int = 0,
-                  nthreads: int = 0, want_stats: bool = True):
+                  nthreads: int = 0, want_stats: bool = True, jac_mode: int = 0):
         """Returns (T_out, Y_out, stats) where stats is a structured numpy array
         (one record per cell) or None.  Inputs are not modified."""
         T = np.array(T, dtype=np.float64, copy=True).ravel()
         n = T.shape[0]
         Y = np.array(Y, dtype=np.float64, copy=True).reshape(self.S, n)
         Y = np.ascontiguousarray(Y)
-        o = OrcOpts(int(max_steps), int(q_max), int(fixed_T), int(fixed_step_n))
+        o = OrcOpts(int(max_steps), int(q_max), int(fixed_T), int(fixed_step_n), int(jac_mode))
         st = (OrcCellStats * n)() if want_stats else None
         self.lib.orc_integrate(self.h, n, _dp(T), _dp(Y), float(p), float(dt), float(rtol), float(atol),
                                C.byref(o), st, int(nthreads))

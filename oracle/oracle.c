@@ -479,6 +479,8 @@ typedef struct {
   int q_max;           /* highest BDF order, 1..5 */
   int fixed_T;         /* hold T constant: f_T = 0, no projection */
   int fixed_step_n;    /* >0: n equal steps, order ramps 1..q_max, no error test, Newton to 1e-10 */
+  int jac_mode;        /* Newton Jacobian: 0 analytic (Eq. 7), 1 difference quotients in every
+                          column, 2 analytic species columns with a difference-quotient T column */
 } orc_opts;
 
 typedef struct {
@@ -572,15 +574,50 @@ static void orc_rescale(int n, double **D, int mdim, double r) {
  * the fast partial equilibria with it, and the next step then sees a jump no
  * step size above the round-off floor can resolve.  The mixture enthalpy is
  * therefore conserved to the integration tolerance. */
+/* Columns j0..N-1 of J = df/dy by one-sided difference quotients at y, the
+ * finite-difference Jacobian the paper compares its analytic one against
+ * (Sec. 3.2; its T column is taken this way in Sec. 3.2.2).  The increment
+ * is the dense difference-quotient rule of the SUNDIALS CVODE documentation:
+ *   inc_j = max(sqrt(u) |y_j|, m / w_j),  m = 1000 |h| u N ||f(y)||_w  (1 if that norm is 0),
+ * with u the unit roundoff, w the error weights and h the current step.
+ * fy = f(y) is given; each column costs one right-hand side.  Returns the
+ * number of right-hand sides evaluated. */
+static int orc_jac_dq(const orc_mech *m, const double *y, double p, int fixed_T, const double *fy,
+                      const double *w, double h, int j0, double *J, double *ytmp, double *f1) {
+  const int S = m->S, N = S + 1;
+  const double u = 2.220446049250313e-16;
+  const double fnorm = orc_wrms(N, fy, w);
+  const double minc = fnorm != 0.0 ? 1000.0 * fabs(h) * u * N * fnorm : 1.0;
+  for (int j = j0; j < N; ++j) {
+    double a = sqrt(u) * fabs(y[j]), b = minc / w[j];
+    double inc = a > b ? a : b;
+    for (int i = 0; i < N; ++i) ytmp[i] = y[i];
+    ytmp[j] = y[j] + inc;
+    orc_rhs(m, ytmp, p, fixed_T, f1);
+    for (int i = 0; i < N; ++i) J[i * N + j] = (f1[i] - fy[i]) / inc;
+  }
+  return N - j0;
+}
+
+/* The difference-quotient Jacobian at one state (all columns), for tests. */
+int orc_jac_fd(const orc_mech *m, const double *y, double p, int fixed_T, const double *w, double h, double *J) {
+  const int N = m->S + 1;
+  double *t = malloc(sizeof(double) * 3 * (size_t)N);
+  orc_rhs(m, y, p, fixed_T, t);
+  int nr = orc_jac_dq(m, y, p, fixed_T, t, w, h, 0, J, t + N, t + 2 * N);
+  free(t);
+  return nr;
+}
+
 static void orc_integrate_cell(const orc_mech *m, double *y, double p, double dt, double rtol, double atol,
                                const orc_opts *o, orc_cell_stats *st) {
   int S = m->S, N = S + 1;
   int q_max = o->q_max < 1 ? 1 : (o->q_max > ORC_QMAX ? ORC_QMAX : o->q_max);
-  double *buf = malloc(sizeof(double) * (size_t)(N * (ORC_QMAX + 3 + 8) + N * N));
+  double *buf = malloc(sizeof(double) * (size_t)(N * (ORC_QMAX + 3 + 10) + N * N));
   double *D[ORC_QMAX + 3];
   for (int j = 0; j < ORC_QMAX + 3; ++j) D[j] = buf + j * N;
   double *w = buf + (ORC_QMAX + 3) * N, *pred = w + N, *psi = pred + N, *d = psi + N, *f = d + N;
-  double *ytmp = f + N, *rhs = ytmp + N, *e = rhs + N, *Mx = e + N;
+  double *ytmp = f + N, *rhs = ytmp + N, *e = rhs + N, *fq = e + N, *yq = fq + N, *Mx = yq + N;
   int *piv = malloc(sizeof(int) * N);
   memset(st, 0, sizeof *st);
   double g[ORC_QMAX + 2];
@@ -632,7 +669,16 @@ static void orc_integrate_cell(const orc_mech *m, double *y, double p, double dt
       psi[i] = ss / g[k];
     }
     double c = h / g[k];
-    orc_jac(m, pred, p, fixedT, Mx);
+    if (o->jac_mode == 1) {
+      orc_rhs(m, pred, p, fixedT, fq);   /* f(pred): the first Newton residual evaluates it again */
+      st->n_rhs += orc_jac_dq(m, pred, p, fixedT, fq, w, h, 0, Mx, yq, e);
+    } else {
+      orc_jac(m, pred, p, fixedT, Mx);
+      if (o->jac_mode == 2) {
+        orc_rhs(m, pred, p, fixedT, fq);
+        st->n_rhs += orc_jac_dq(m, pred, p, fixedT, fq, w, h, S, Mx, yq, e);
+      }
+    }
     st->n_jac++;
     for (int i = 0; i < N; ++i)
       for (int j = 0; j < N; ++j) Mx[i * N + j] = (i == j ? 1.0 : 0.0) - c * Mx[i * N + j];

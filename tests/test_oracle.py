@@ -8,7 +8,8 @@ by re-typing the oracle's own formulas.
   Lindemann reactions, and the A <-> B relaxation
 * Jacobian (Eq. 7): complex-step derivative of an independent rhs, the paper's
   Eq. 10 error metric against central differences, first-order convergence of
-  one-sided differences (App. C)
+  one-sided differences (App. C); the integrator's difference-quotient
+  Jacobian modes against the complex-step Jacobian and the truth reference
 * LU: numpy.linalg.solve; enthalpy inversion: numpy.roots
 * integrator: conservation of elements, sum(Y) and enthalpy (to tolerance); detailed balance
   at long times; convergence order 1 and 2 with fixed steps; agreement with
@@ -301,6 +302,46 @@ def test_jacobian_eq9_and_one_sided_fd_order(g10):
         e.append(np.linalg.norm(col - J[:, j]) / np.linalg.norm(J[:, j]))
     slope = np.polyfit(np.log(hs), np.log(e), 1)[0]
     assert 0.8 < slope < 1.2
+
+
+def test_difference_quotient_jacobian(g10):
+    """The integrator's finite-difference Jacobian (Sec. 3.2): one-sided
+    quotients with the increment max(sqrt(u)|y_j|, m/w_j).  Against the
+    complex-step Jacobian its relative Frobenius error (Eq. 10) is of the
+    order of the increment, sqrt(u) ~ 1.5e-8, times the curvature of f."""
+    for cfg in (1, 4):
+        m = synth.config_mechanism(cfg)
+        om = oracle.Mech(m.to_text())
+        errs = []
+        for s, T in enumerate((900.0, 1400.0, 2200.0)):
+            y = state(m, T, 40 + s)
+            Jcs = rhs_numpy.jac_complex_step(m, y, P)
+            w = 1.0 / (1e-8 * np.abs(y) + 1e-12)
+            f = om.rhs(y, P)
+            h = 1.0 / math.sqrt(np.mean((f * w) ** 2))      # a step the integrator would take here
+            Jfd = om.jac_fd(y, P, w, h)
+            errs.append(np.linalg.norm(Jfd - Jcs) / np.linalg.norm(Jcs))
+        assert max(errs) < 1e-5, (cfg, errs)
+        assert min(errs) > 1e-12          # a difference quotient, not the analytic Jacobian
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_integration_with_difference_quotient_jacobian(g10, g10_run, mode):
+    """With the finite-difference Jacobian (all columns, or only the T column
+    as in Sec. 3.2.2) Newton converges to the same corrector equations: the
+    result matches the tight-tolerance truth to a small multiple of rtol, at
+    the price of extra right-hand sides (N per Jacobian, or one)."""
+    m, om = g10
+    w, T, Y, st = g10_run
+    idx = np.arange(0, 48, 4)
+    Tt, Yt, _ = om.integrate(w.T[idx], w.Y[:, idx], w.p, w.dt, 1e-12, 1e-20)
+    Tf, Yf, sf = om.integrate(w.T[idx], w.Y[:, idx], w.p, w.dt, w.rtol, w.atol, jac_mode=mode)
+    assert (sf["status"] == 0).all()
+    assert np.abs(Yf - Yt).max() <= 1e-7
+    assert (np.abs(Tf - Tt) / Tt).max() <= 1e-7
+    extra = sf["n_rhs"] - sf["n_newton"] - 1          # right-hand sides beyond the Newton residuals
+    per_jac = m.n_species + 1 if mode == 1 else 1
+    assert (extra == per_jac * sf["n_jac"]).all()
 
 
 # ----------------------------------------------------------- linear algebra

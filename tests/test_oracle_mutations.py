@@ -161,6 +161,18 @@ def pin_enthalpy_conservation(lib):
     return bool(ok)
 
 
+def pin_difference_quotient(lib):
+    m = synth.config_mechanism(1)
+    om = oracle.Mech(m.to_text(), lib_path=lib)
+    rng = np.random.default_rng(9)
+    y = np.concatenate([synth.composition(rng, m.n_species, 1.0, 1)[:, 0], [1400.0]])
+    Jcs = rhs_numpy.jac_complex_step(m, y, P)
+    w = 1.0 / (1e-8 * np.abs(y) + 1e-12)
+    f = om.rhs(y, P)
+    Jfd = om.jac_fd(y, P, w, 1.0 / math.sqrt(np.mean((f * w) ** 2)))
+    return bool(np.linalg.norm(Jfd - Jcs) / np.linalg.norm(Jcs) < 1e-5)
+
+
 MUTATIONS = [
     ("standard-state exponent sign", "pow(c0, (double)dnu)", "pow(c0, (double)-dnu)", pin_gibbs_minimum),
     ("third body drops [M]", "if (x->type == 1) q *= Mconc;", "if (x->type == 9) q *= Mconc;",
@@ -177,6 +189,8 @@ MUTATIONS = [
     ("enthalpy inversion sign", "double c = h - al;", "double c = al - h;", pin_enthalpy_inversion),
     ("sign of the temperature equation", "f[S] = fixed_T ? 0.0 : -num / den;", "f[S] = fixed_T ? 0.0 : num / den;",
      pin_enthalpy_conservation),
+    ("difference quotient off by the increment", "ytmp[j] = y[j] + inc;", "ytmp[j] = y[j] + 2.0 * inc;",
+     pin_difference_quotient),
 ]
 
 
