@@ -59,10 +59,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16384, help="cells in the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--q-max", type=int, default=5)
-    ap.add_argument("--mode", choices=["flame", "boxes", "serve", "copy"], default="flame",
+    ap.add_argument("--mode", choices=["flame", "boxes", "serve", "copy", "jacstudy"], default="flame",
                     help="flame: the headline box; boxes: uneven AMR boxes in one persistent launch; "
                          "serve: Poisson request trace through the continuous-batching server; "
-                         "copy: a plain device copy of known size (HBM counter calibration)")
+                         "copy: a plain device copy of known size (HBM counter calibration); "
+                         "jacstudy: analytic vs finite-difference Newton Jacobian at S = 10, 30, 53")
     ap.add_argument("--lu-fp32", action="store_true", help="FP32 Newton-matrix LU with FP64 refinement")
     ap.add_argument("--kernel", choices=["auto", "group", "lane"], default="auto",
                     help="kernel family: lane = generated lane-per-cell kernels (S+1 <= 12), group = 16-64 lanes "
@@ -89,6 +90,8 @@ def main():
         return bench_boxes(args, torch, dev, chem, synth)
     if args.mode == "serve":
         return bench_serve(args, torch, dev, chem, synth)
+    if args.mode == "jacstudy":
+        return bench_jacstudy(args, torch, dev, chem, synth)
     shape = tuple(int(v) for v in args.shape.split(",")) if args.shape else None
     w = synth.config_workload(args.config, os.path.join(ROOT, "tests", "golden"), shape=shape)
     shape = w.shape if w.shape else shape
@@ -301,6 +304,51 @@ def bench_boxes(args, torch, dev, chem, synth):
                    "cells": n, "group_width": width, "waves_per_cu": waves},
         "integration": {"steps_per_cell": stats["n_steps_total"] / n, "failed_cells": stats["n_cells_failed"]},
     }), flush=True)
+
+
+def bench_jacstudy(args, torch, dev, chem, synth):
+    """The paper's analytic-vs-finite-difference Jacobian comparison (Sec. 3.2,
+    the speedup column of its Table 4) on the GPU: the same cells integrated
+    by the group kernels with the analytic Jacobian, with difference quotients
+    in every column, and with only the temperature column by differences
+    (Sec. 3.2.2).  Mechanisms G(10,25,3), G(30,180,4), G(53,325,4); flame-box
+    states for S = 10 and 53, AMR-box states for S = 30.  One timed call per
+    (mechanism, mode) after a warm-up call."""
+    golden = os.path.join(ROOT, "tests", "golden")
+    cases = []
+    w2 = synth.config_workload(2, golden, shape=(256, 4, 4))
+    cases.append(("G(10,25,3,seed 1)", w2.mech, w2.T, w2.Y, w2.dt, w2.rtol, w2.atol, "flame 256x4x4"))
+    m4 = synth.config_mechanism(4)
+    bx = synth.amr_boxes(m4, 64, synth.config_seed(4), max_cells=64)
+    T4 = np.concatenate([b.T for b in bx])[:2048]
+    Y4 = np.concatenate([b.Y for b in bx], axis=1)[:, :2048]
+    cases.append(("G(30,180,4,seed 3)", m4, T4, Y4, 1e-6, 1e-8, 1e-12, f"AMR-box states, dt 1e-6 s"))
+    w3 = synth.config_workload(3, golden, shape=(256, 2, 2))
+    cases.append(("G(53,325,4,seed 2)", w3.mech, w3.T, w3.Y, w3.dt, w3.rtol, w3.atol, "flame 256x2x2"))
+    rows = []
+    for name, m, T0n, Y0n, dt, rtol, atol, what in cases:
+        gm = chem.Mechanism(m.to_text())
+        T0 = torch.tensor(np.asarray(T0n, dtype=np.float64), device=dev)
+        Y0 = torch.tensor(np.ascontiguousarray(Y0n, dtype=np.float64), device=dev)
+        row = {"mechanism": name, "species": m.n_species, "reactions": m.n_reactions, "cells": int(T0.numel()),
+               "states": what, "dt": dt, "rtol": rtol}
+        for mode, key in ((0, "analytic"), (1, "fd"), (2, "fd_T")):
+            gm.set_options(q_max=args.q_max, kernel=KERNEL_CODES["group"], jac=mode)
+            T, Y = T0.clone(), Y0.clone()
+            gm.integrate(T, Y, synth.P_ATM, dt, rtol, atol)                       # warm-up
+            T.copy_(T0)
+            Y.copy_(Y0)
+            st = gm.integrate(T, Y, synth.P_ATM, dt, rtol, atol)
+            n = T0.numel()
+            row[key] = {"kernel_ms": st["wall_ms"], "steps_per_cell": st["n_steps_total"] / n,
+                        "rhs_per_cell": st["n_rhs"] / n, "newton_per_cell": st["n_newton_iters"] / n,
+                        "failed_cells": st["n_cells_failed"]}
+            print(f"jacstudy {name} {key}: {st['wall_ms']:.1f} ms", file=sys.stderr, flush=True)
+        row["speedup_analytic_vs_fd"] = row["fd"]["kernel_ms"] / row["analytic"]["kernel_ms"]
+        row["speedup_analytic_vs_fd_T"] = row["fd_T"]["kernel_ms"] / row["analytic"]["kernel_ms"]
+        rows.append(row)
+    print(json.dumps({"mode": "jacstudy", "dtype": "f64", "data": "synthetic", "kernel": "group kernels",
+                      "rows": rows}), flush=True)
 
 
 def bench_serve(args, torch, dev, chem, synth):

@@ -81,7 +81,14 @@ typedef struct {
 #define CHEM_OPT_GROUP_WIDTH 9  /* lanes per cell: 16, 32 or 64, at least S+1 (default: the smallest) */
 #define CHEM_OPT_KERNEL 10      /* kernel family: 0 auto (default), 1 group kernels (16-64 lanes per cell),
                                    2 lane-per-cell kernels generated for the mechanism and compiled at run
-                                   time (S+1 <= 12, FP64 LU only; auto picks them where they apply) */
+                                   time (S+1 <= 12, FP64 LU and analytic Jacobian only; auto picks them
+                                   where they apply) */
+#define CHEM_OPT_JAC 11         /* Newton Jacobian (Sec. 3.2): 0 analytic, Eq. 7 (default); 1 one-sided
+                                   difference quotients in every column (N extra right-hand sides per
+                                   Jacobian); 2 analytic species columns with a difference-quotient
+                                   temperature column, as in Sec. 3.2.2 (one extra right-hand side).
+                                   Increment of column j: max(sqrt(u)|y_j|, 1000 h u N ||f||_w / w_j),
+                                   u the FP64 unit roundoff, w the error weights.  Group kernels only */
 
 /* Parse a mechanism from a file path / from text (format "chem-mech 1":
  * elements with masses; species with atom counts, inert flag and linear

@@ -322,9 +322,10 @@ int chem_select_kernel(chem_mech* m, bool* lpc) {
       return fail(CHEM_ERR_UNSUPPORTED,
                   "lane-per-cell kernels serve up to " + std::to_string(chemgpu::kLpcMaxN) + " state components");
     if (m->lu_fp32) return fail(CHEM_ERR_UNSUPPORTED, "the FP32-LU option runs in the group kernels only");
+    if (m->jac_mode) return fail(CHEM_ERR_UNSUPPORTED, "finite-difference Jacobians run in the group kernels only");
     want = true;
   } else if (m->kernel_mode == 0) {
-    want = N <= chemgpu::kLpcMaxN && !m->lu_fp32;
+    want = N <= chemgpu::kLpcMaxN && !m->lu_fp32 && !m->jac_mode;
   }
   *lpc = want;
   if (!want) return CHEM_OK;
@@ -436,6 +437,11 @@ int chem_set_option(chem_mech* m, int key, double value) {
       if (v < 1 || v > 32) return fail(CHEM_ERR_ARG, "waves_per_cu must be 1..32");
       m->waves_per_cu = (int)v;
       return CHEM_OK;
+    case CHEM_OPT_JAC:
+      if (v != 0 && v != 1 && v != 2)
+        return fail(CHEM_ERR_ARG, "jac must be 0 (analytic), 1 (difference quotients) or 2 (difference-quotient T column)");
+      m->jac_mode = (int)v;
+      return CHEM_OK;
     case CHEM_OPT_KERNEL:
       if (v != 0 && v != 1 && v != 2) return fail(CHEM_ERR_ARG, "kernel must be 0 (auto), 1 (group) or 2 (lane per cell)");
       m->kernel_mode = (int)v;
@@ -482,6 +488,7 @@ int chem_integrate_ex(chem_mech* m, int64_t n_cells, double* T, double* Y, doubl
   prm.fixed_step_n = m->fixed_step_n;
   prm.lu_fp32 = m->lu_fp32;
   prm.ir_max = m->ir_max;
+  prm.jac_mode = m->jac_mode;
   bool lpc = false;
   const int krc = chem_select_kernel(m, &lpc);
   if (krc != CHEM_OK) return krc;
@@ -616,6 +623,7 @@ int chem_integrate_boxes(chem_mech* m, int n_boxes, const chem_box* boxes, doubl
     prm.fixed_step_n = m->fixed_step_n;
     prm.lu_fp32 = m->lu_fp32;
     prm.ir_max = m->ir_max;
+    prm.jac_mode = m->jac_mode;
     const int grid = (int)std::min<int64_t>(tiles, (int64_t)m->waves_per_cu * m->n_cu);
     const auto t0 = std::chrono::steady_clock::now();
     e = hipEventRecord(m->ev0, m->stream);

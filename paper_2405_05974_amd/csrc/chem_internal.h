@@ -69,6 +69,7 @@ struct IntParams {
   double p, dt, rtol, atol;
   int max_steps, q_max, fixed_T, fixed_step_n;
   int lu_fp32, ir_max;
+  int jac_mode;   // 0 analytic Jacobian, 1 difference quotients, 2 analytic with a difference-quotient T column
 };
 
 // Launchers (chem_kernels.hip).  All enqueue on `stream` and return the HIP

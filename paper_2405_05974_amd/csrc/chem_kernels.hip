@@ -550,6 +550,46 @@ __device__ __forceinline__ double wrms(const double v, const double w, const int
   return M * sqrt(gsum<NP>(u * u) / N);
 }
 
+// Columns j0..N-1 of the group's Jacobian rows by one-sided difference
+// quotients at y (component yr on lane r), given fy = f(y): the
+// finite-difference Jacobian of Sec. 3.2 (the temperature column alone,
+// j0 = N-1, in Sec. 3.2.2).  The increment of column j is
+// max(sqrt(u) |y_j|, m / w_j) with m = 1000 |h| u N ||f(y)||_w (1 when the
+// norm is 0) and u the FP64 unit roundoff, the dense difference-quotient rule
+// of the SUNDIALS CVODE documentation.  With j0 = 0 the columns N..NP-1 of the
+// stored rows are cleared as well.  Returns the right-hand sides evaluated.
+template <int NP>
+__device__ __forceinline__ int jac_difference_quotients(const DevMech& m, const Spc& sc, const double p,
+                                                        const int fixedT, const double yr, const double fy,
+                                                        const double w, const double h, const int N,
+                                                        const int j0, const Shared& sh) {
+  const int lane = opaque_lane();
+  const int r = lane % NP;
+  const int base = lane - r;
+  double* Jg = sh.J + (size_t)(lane / NP) * sh.rows * sh.ldj;
+  const double u = DBL_EPSILON;
+  const double fnorm = wrms<NP>(fy, w, N);
+  const double minc = fnorm != 0.0 ? 1000.0 * fabs(h) * u * N * fnorm : 1.0;
+  double mine = 0.0;
+  if (r < N) {
+    const double a = sqrt(u) * fabs(yr), b = minc / w;
+    mine = a > b ? a : b;
+  }
+  if (j0 == 0 && r < sh.rows) {
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+      if (c >= N) Jg[r * sh.ldj + c] = 0.0;
+  }
+  for (int j = j0; j < N; ++j) {
+    const double inc = __shfl(mine, base + j);
+    double f1, wdx;
+    rhs_eval<NP, false>(m, sc, p, fixedT, yr + ((r == j) ? inc : 0.0), f1, wdx, sh);
+    if (r < N) Jg[r * sh.ldj + j] = (f1 - fy) / inc;
+  }
+  wave_sync();
+  return N - j0;
+}
+
 // Mixed-precision option: the same pivoted factorisation of M = I - c J in
 // FP32 (M rounded from FP64), factors kept in FP32 LDS rows in pivot order;
 // J stays in FP64 for the refinement residuals.
@@ -791,7 +831,14 @@ __device__ __forceinline__ void integrate_group(const DevMech& m, const IntParam
       const double c = h / gk;
 
       double fp;
-      rhs_eval<NP, true>(m, sc, P.p, fixedT, pred, fp, wdx, sh);
+      if (P.jac_mode == 1) {
+        // f(pred) serves the quotients and the first Newton residual
+        rhs_eval<NP, false>(m, sc, P.p, fixedT, pred, fp, wdx, sh);
+        nrhs += jac_difference_quotients<NP>(m, sc, P.p, fixedT, pred, fp, w, h, N, 0, sh);
+      } else {
+        rhs_eval<NP, true>(m, sc, P.p, fixedT, pred, fp, wdx, sh);
+        if (P.jac_mode == 2) nrhs += jac_difference_quotients<NP>(m, sc, P.p, fixedT, pred, fp, w, h, N, N - 1, sh);
+      }
       njac++;
       double rdiag = 0.0;
       float rdiag32 = 0.0f;

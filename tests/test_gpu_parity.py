@@ -290,6 +290,58 @@ def test_config4_mechanism_sample(chem, torch_dev):
         assert_parity(Tg, Yg, To, Yo, f"config4 box {bi}")
 
 
+# A difference quotient (f(y + d e_j) - f(y)) / d with d ~ sqrt(u)|y_j| carries a
+# rounding error of about u|f|/d ~ sqrt(u) ~ 1.5e-8 relative, so two correct
+# implementations' finite-difference Jacobians differ at that level.  Newton
+# then stops at different iterates within its tolerance and later step
+# decisions can differ: the results agree to the integration accuracy, not to
+# rounding.  On these inputs the oracle's own finite-difference runs are within
+# 1.3e-7 (T) and 2.3e-8 (Y) of the tight-tolerance truth; the bar below allows
+# the GPU the same distance from the oracle and from the truth.
+TOL_FD_Y = 1e-7
+TOL_FD_T = 3e-7
+
+
+@pytest.mark.parametrize("mode", [1, 2], ids=["fd", "fd_T"])
+def test_difference_quotient_jacobian_parity(chem, torch_dev, mode):
+    """Finite-difference Newton Jacobians (every column, Sec. 3.2; only the
+    temperature column, Sec. 3.2.2) in the group kernels against the same modes
+    of the oracle and against the tight-tolerance truth, on a config-1 sample
+    and on a config-4 box (S = 30)."""
+    import oracle
+    w = synth.config_workload(1)
+    idx = np.arange(0, w.n_cells, 16)
+    text = w.mech.to_text()
+    say(f"jacobian mode {mode}: config1 n={idx.size}")
+    Tg, Yg, st, rec = gpu_integrate(chem, torch_dev, text, w.T[idx], w.Y[:, idx], w.p, w.dt, w.rtol, w.atol,
+                                    jac=mode)
+    To, Yo, so = oracle_integrate(text, w.T[idx], w.Y[:, idx], w.p, w.dt, w.rtol, w.atol, jac_mode=mode)
+    Tt, Yt, _ = oracle.Mech(text).integrate(w.T[idx], w.Y[:, idx], w.p, w.dt, 1e-12, 1e-20)
+    assert st["rc"] == 0 and (rec[0] == 0).all()
+    for what, (Ta, Ya, Tb, Yb) in (("vs oracle", (Tg, Yg, To, Yo)), ("vs truth", (Tg, Yg, Tt, Yt))):
+        dY = np.abs(Ya - Yb).max()
+        dT = (np.abs(Ta - Tb) / Tb).max()
+        say(f"jacobian mode {mode} config1 {what}: max|dY|={dY:.3e} max|dT|/T={dT:.3e}")
+        assert dY <= TOL_FD_Y and dT <= TOL_FD_T, what
+    say(f"jacobian mode {mode}: steps gpu {rec[1].sum()} oracle {so['steps'].sum()}, "
+        f"identical per cell {(rec[1] == so['steps']).mean():.3f}")
+    assert abs(rec[1].sum() / so["steps"].sum() - 1) <= 0.05
+    # right-hand sides: one per cell to start, one per Newton iteration, and the quotients
+    per_jac = w.mech.n_species + 1 if mode == 1 else 1
+    assert st["n_rhs"] == st["n_cells"] + st["n_newton_iters"] + per_jac * st["n_jac"]
+    m4 = synth.config_mechanism(4)
+    bx = synth.amr_boxes(m4, 3, synth.config_seed(4), max_cells=24)[2]
+    text4 = m4.to_text()
+    say(f"jacobian mode {mode}: config4 box n={bx.T.size} dt={bx.dt:.3e}")
+    Tg, Yg, st, rec = gpu_integrate(chem, torch_dev, text4, bx.T, bx.Y, synth.P_ATM, bx.dt, 1e-8, 1e-12, jac=mode)
+    To, Yo, so = oracle_integrate(text4, bx.T, bx.Y, synth.P_ATM, bx.dt, 1e-8, 1e-12, jac_mode=mode)
+    assert st["rc"] == 0
+    dY = np.abs(Yg - Yo).max()
+    dT = (np.abs(Tg - To) / To).max()
+    say(f"jacobian mode {mode} config4 box: max|dY|={dY:.3e} max|dT|/T={dT:.3e}")
+    assert dY <= TOL_FD_Y and dT <= TOL_FD_T
+
+
 def test_config3_sample(chem, torch_dev):
     w = synth.config_workload(3, GOLDEN, shape=(256, 1, 1))
     idx = np.arange(0, 256, 16)
@@ -502,5 +554,8 @@ def test_lane_kernel_boxes_and_unsupported_requests(chem, torch_dev):
     with pytest.raises(chem.ChemError):
         big.integrate(T, Y, synth.P_ATM, 1e-7, 1e-8, 1e-12)
     gm.set_options(lu_fp32=1)
+    with pytest.raises(chem.ChemError):
+        gm.integrate(tens[0][0], tens[0][1], synth.P_ATM, 1e-7, 1e-8, 1e-12)
+    gm.set_options(lu_fp32=0, jac=1)        # finite-difference Jacobians: group kernels only
     with pytest.raises(chem.ChemError):
         gm.integrate(tens[0][0], tens[0][1], synth.P_ATM, 1e-7, 1e-8, 1e-12)
