@@ -32,7 +32,7 @@ def build(extra_flags=()) -> str:
 
 class OrcOpts(C.Structure):
     _fields_ = [("max_steps", C.c_int), ("q_max", C.c_int), ("fixed_T", C.c_int),
-                ("fixed_step_n", C.c_int), ("jac_mode", C.c_int)]
+                ("fixed_step_n", C.c_int), ("jac_mode", C.c_int), ("jac_reuse", C.c_int)]
 
 
 class OrcCellStats(C.Structure):
@@ -168,14 +168,14 @@ class Mech:
     # -- whole-batch integration ---------------------------------------------
     def integrate(self, T: np.ndarray, Y: np.ndarray, p: float, dt: float, rtol: float, atol: float,
                   max_steps: int = 100000, q_max: int = 5, fixed_T: bool = False, fixed_step_n: int = 0,
-                  nthreads: int = 0, want_stats: bool = True, jac_mode: int = 0):
+                  nthreads: int = 0, want_stats: bool = True, jac_mode: int = 0, jac_reuse: bool = True):
         """Returns (T_out, Y_out, stats) where stats is a structured numpy array
         (one record per cell) or None.  Inputs are not modified."""
         T = np.array(T, dtype=np.float64, copy=True).ravel()
         n = T.shape[0]
         Y = np.array(Y, dtype=np.float64, copy=True).reshape(self.S, n)
         Y = np.ascontiguousarray(Y)
-        o = OrcOpts(int(max_steps), int(q_max), int(fixed_T), int(fixed_step_n), int(jac_mode))
+        o = OrcOpts(int(max_steps), int(q_max), int(fixed_T), int(fixed_step_n), int(jac_mode), int(jac_reuse))
         st = (OrcCellStats * n)() if want_stats else None
         self.lib.orc_integrate(self.h, n, _dp(T), _dp(Y), float(p), float(dt), float(rtol), float(atol),
                                C.byref(o), st, int(nthreads))

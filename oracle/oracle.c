@@ -24,9 +24,10 @@
  *       dY_k/dt = W_k wdot_k / rho,  dT/dt = -sum_k H_k wdot_k / sum_k C_k Cp_k
  *   - species thermo with linear heat capacity cp/R = a0 + a1 T.
  *   - quasi-constant-step BDF in backward-difference form, orders 1-5, a
- *     fresh Jacobian and LU every step, WRMS error control, and after every
- *     accepted step projection of Y onto Y >= 0 (steps that would leave a
- *     mass fraction below -atol are rejected).
+ *     factored Newton matrix kept while recent (or fresh every step), WRMS
+ *     error control, and after every accepted step projection of Y onto
+ *     Y >= 0 (steps that would leave a mass fraction below -atol are
+ *     rejected).
  * Units: the interface is SI (K, Pa, s, mass fractions); concentrations and
  * rate constants are cgs (mol/cm^3, A in mol-cm-s units).
  *
@@ -481,6 +482,8 @@ typedef struct {
   int fixed_step_n;    /* >0: n equal steps, order ramps 1..q_max, no error test, Newton to 1e-10 */
   int jac_mode;        /* Newton Jacobian: 0 analytic (Eq. 7), 1 difference quotients in every
                           column, 2 analytic species columns with a difference-quotient T column */
+  int jac_reuse;       /* 1: keep the factored Newton matrix across attempts while it is recent
+                          (see orc_integrate_cell); 0: a fresh Jacobian and LU every attempt */
 } orc_opts;
 
 typedef struct {
@@ -643,6 +646,8 @@ static void orc_integrate_cell(const orc_mech *m, double *y, double p, double dt
   }
   for (int i = 0; i < N; ++i) D[1][i] = h * f[i];
   int k = 1, etf = 0, nk = 0;   /* nk: accepted steps since the last change of h or order */
+  int have_lu = 0, steps_lu = 0, stale_fail = 0;   /* state of the factored Newton matrix */
+  double c_lu = 0.0;
   double t = 0.0;
   while (t < dt) {
     if (st->attempts >= o->max_steps) { st->status = 1; break; }
@@ -669,20 +674,34 @@ static void orc_integrate_cell(const orc_mech *m, double *y, double p, double dt
       psi[i] = ss / g[k];
     }
     double c = h / g[k];
-    if (o->jac_mode == 1) {
-      orc_rhs(m, pred, p, fixedT, fq);   /* f(pred): the first Newton residual evaluates it again */
-      st->n_rhs += orc_jac_dq(m, pred, p, fixedT, fq, w, h, 0, Mx, yq, e);
-    } else {
-      orc_jac(m, pred, p, fixedT, Mx);
-      if (o->jac_mode == 2) {
-        orc_rhs(m, pred, p, fixedT, fq);
-        st->n_rhs += orc_jac_dq(m, pred, p, fixedT, fq, w, h, S, Mx, yq, e);
+    /* Newton matrix M = I - c J, factored.  With reuse (CVODE's policy for
+     * its Newton matrix, Sec. 3.2) the factors of an earlier attempt are kept
+     * while they are recent: c within 30% of the c they were formed with,
+     * fewer than 20 accepted steps since, and no Newton failure with them
+     * (a failure retries the same step with a fresh matrix).  Otherwise the
+     * Jacobian is evaluated at the predictor and M factored afresh. */
+    int fresh = !o->jac_reuse || !have_lu || fabs(c / c_lu - 1.0) > 0.3 || st->steps - steps_lu >= 20 ||
+                stale_fail;
+    if (fresh) {
+      if (o->jac_mode == 1) {
+        orc_rhs(m, pred, p, fixedT, fq);   /* f(pred): the first Newton residual evaluates it again */
+        st->n_rhs += orc_jac_dq(m, pred, p, fixedT, fq, w, h, 0, Mx, yq, e);
+      } else {
+        orc_jac(m, pred, p, fixedT, Mx);
+        if (o->jac_mode == 2) {
+          orc_rhs(m, pred, p, fixedT, fq);
+          st->n_rhs += orc_jac_dq(m, pred, p, fixedT, fq, w, h, S, Mx, yq, e);
+        }
       }
+      st->n_jac++;
+      for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) Mx[i * N + j] = (i == j ? 1.0 : 0.0) - c * Mx[i * N + j];
+      orc_lu(N, Mx, piv);
+      have_lu = 1;
+      c_lu = c;
+      steps_lu = st->steps;
+      stale_fail = 0;
     }
-    st->n_jac++;
-    for (int i = 0; i < N; ++i)
-      for (int j = 0; j < N; ++j) Mx[i * N + j] = (i == j ? 1.0 : 0.0) - c * Mx[i * N + j];
-    orc_lu(N, Mx, piv);
     for (int i = 0; i < N; ++i) d[i] = 0.0;
     int conv = 0;
     double prev = 0.0;
@@ -700,6 +719,11 @@ static void orc_integrate_cell(const orc_mech *m, double *y, double p, double dt
       if (nrm <= ntol) { conv = 1; break; }
       if (it > 1 && nrm > 2.0 * prev) break;
       prev = nrm;
+    }
+    if (!conv && !fixed && !fresh) {   /* a kept matrix failed: same step, fresh matrix */
+      st->n_nnf++;
+      stale_fail = 1;
+      continue;
     }
     if (!conv && !fixed) {
       st->n_nnf++;

@@ -425,6 +425,28 @@ def test_integration_against_tight_reference(g10, g10_run):
     assert e1 < e2 / 10                 # tighter tolerance, smaller error
 
 
+def test_newton_matrix_reuse(g10, g10_run):
+    """Keeping the factored Newton matrix while it is recent (the default)
+    changes how Newton converges, not what it converges to: the result stays
+    within a small multiple of rtol of the truth, like the fresh-every-attempt
+    run, while most attempts skip the Jacobian and the factorisation."""
+    m, om = g10
+    w, T, Y, st = g10_run
+    idx = np.arange(0, 48, 3)
+    Tt, Yt, _ = om.integrate(w.T[idx], w.Y[:, idx], w.p, w.dt, 1e-12, 1e-20, jac_reuse=False)
+    Tf, Yf, sf = om.integrate(w.T[idx], w.Y[:, idx], w.p, w.dt, w.rtol, w.atol, jac_reuse=False)
+    assert (sf["n_jac"] == sf["attempts"]).all()
+    for Ta, Ya in ((T[idx], Y[:, idx]), (Tf, Yf)):
+        assert np.abs(Ya - Yt).max() <= 1e-7
+        assert (np.abs(Ta - Tt) / Tt).max() <= 2e-7
+    assert st["n_jac"][idx].sum() < 0.3 * st["attempts"][idx].sum()
+    # linear invariants hold for any Jacobian with the same left null space
+    # (exactly where the positivity projection never fired)
+    dm = np.abs(Y[:, idx].sum(axis=0) - 1.0)
+    clean = st["n_clip"][idx] == 0
+    assert clean.any() and dm[clean].max() <= 1e-13 and dm.max() <= 1e-8
+
+
 def test_q_max_two_also_converges(g10, g10_run):
     m, om = g10
     w, T, Y, st = g10_run
