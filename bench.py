@@ -29,21 +29,24 @@ C_EXP = 20.0                     # FP64 flops charged per exp/log (software sequ
 
 def flop_model(S: int, R: int, n_tb: int, n_falloff: int):
     """Algorithmic FP64 flops per event of the method:
-    per rhs evaluation, per Jacobian + Newton-matrix + LU (one per attempt),
-    per Newton iteration (residual, solve, norm)."""
+    per rhs evaluation, per fresh Newton matrix (Jacobian extra work, M = I - cJ
+    and its LU; one per attempt unless factors are kept), per attempt (step
+    control), per Newton iteration (residual, solve, norm)."""
     N = S + 1
     nnz = 4 * R                                   # nonzeros of nu (<= 2 + 2 per reaction)
     f_rhs = 32 * S + S * C_EXP + R * (26 + 2 * C_EXP) + n_falloff * (8 + C_EXP) + n_tb + 2 * nnz
     f_jac = 26 * R + 12 * nnz + 13 * S * S + 10 * N
     f_lu = 2.0 * N ** 3 / 3.0
-    f_attempt = f_jac + 2 * N * N + f_lu + 40 * N
+    f_setup = f_jac + 2 * N * N + f_lu
+    f_control = 40 * N
     f_newton = 2 * N * N + 7 * N
-    return f_rhs, f_attempt, f_newton
+    return f_rhs, f_setup, f_control, f_newton
 
 
 def algorithmic_flops(stats, S, R, n_tb, n_falloff):
-    f_rhs, f_attempt, f_newton = flop_model(S, R, n_tb, n_falloff)
-    return stats["n_rhs"] * f_rhs + stats["n_attempts"] * f_attempt + stats["n_newton_iters"] * f_newton
+    f_rhs, f_setup, f_control, f_newton = flop_model(S, R, n_tb, n_falloff)
+    return (stats["n_rhs"] * f_rhs + stats["n_jac"] * f_setup + stats["n_attempts"] * f_control
+            + stats["n_newton_iters"] * f_newton)
 
 
 def main():
@@ -65,6 +68,9 @@ def main():
                          "copy: a plain device copy of known size (HBM counter calibration); "
                          "jacstudy: analytic vs finite-difference Newton Jacobian at S = 10, 30, 53")
     ap.add_argument("--lu-fp32", action="store_true", help="FP32 Newton-matrix LU with FP64 refinement")
+    ap.add_argument("--jac-reuse", action="store_true",
+                    help="keep the factored Newton matrix across attempts while it is recent (CVODE's policy); "
+                         "default: a fresh Jacobian and LU every attempt")
     ap.add_argument("--kernel", choices=["auto", "group", "lane"], default="auto",
                     help="kernel family: lane = generated lane-per-cell kernels (S+1 <= 12), group = 16-64 lanes "
                          "per cell; auto picks lane where it applies")
@@ -100,7 +106,8 @@ def main():
     n_tb = sum(r.kind == 1 for r in m.reactions)
     n_fo = sum(r.kind == 2 for r in m.reactions)
     gm = chem.Mechanism(m.to_text())
-    gm.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32), kernel=KERNEL_CODES[args.kernel])
+    gm.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32), kernel=KERNEL_CODES[args.kernel],
+                   jac_reuse=int(args.jac_reuse))
     kname = kernel_name(args, m.n_species + 1)
     T0 = torch.tensor(w.T, dtype=torch.float64, device=dev)
     Y0 = torch.tensor(w.Y, dtype=torch.float64, device=dev)
@@ -154,7 +161,8 @@ def main():
             "workload": (f"planar flame box {shape[0]}x{shape[1]}x{shape[2]} = {n} cells, mechanism "
                          f"G{synth.CONFIG_MECH[args.config][:3]} seed {synth.CONFIG_MECH[args.config][3]}, "
                          f"T 300->2200 K tanh profile, dt {w.dt:g} s, rtol {w.rtol:g}, "
-                         f"atol {w.atol:g}, p 1 atm, constant-pressure adiabatic, BDF q<={args.q_max}"),
+                         f"atol {w.atol:g}, p 1 atm, constant-pressure adiabatic, BDF q<={args.q_max}, "
+                         + ("Newton matrix kept while recent" if args.jac_reuse else "fresh Newton matrix every attempt")),
             "cells": n, "species": m.n_species, "reactions": m.n_reactions,
             "parallelism": "none (1 GPU)",
         },
@@ -219,7 +227,7 @@ def cpu_baseline(w, Tg, Yg, args):
     print(f"cpu baseline: oracle on {idx.size} cells, {threads} threads", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     To, Yo, so = om.integrate(w.T[idx], w.Y[:, idx], w.p, w.dt, w.rtol, w.atol, q_max=args.q_max,
-                              nthreads=threads)
+                              nthreads=threads, jac_reuse=args.jac_reuse)
     el = time.perf_counter() - t0
     print(f"cpu baseline: {el:.1f} s", file=sys.stderr, flush=True)
     Tgs = Tg.cpu().numpy()[idx]
@@ -228,14 +236,15 @@ def cpu_baseline(w, Tg, Yg, args):
            "max_abs_dY": float(np.abs(Ygs - Yo).max()),
            "max_rel_dT": float((np.abs(Tgs - To) / To).max()),
            "p99_abs_dY": float(np.percentile(np.abs(Ygs - Yo).max(axis=0), 99))}
-    # against the tight-tolerance truth (the oracle at rtol 1e-12, atol 1e-20) on a sub-sample of at
-    # most 256 cells, skipped where one truth cell would take over a minute on one core (the tight
-    # run takes about 8x the same-settings time)
-    per_cell_1core = el * threads / idx.size
-    if 8.0 * per_cell_1core > 60.0:
-        acc["vs_truth"] = {"cells": 0, "what": f"skipped: about {8.0 * per_cell_1core:.0f} s per truth cell on one core"}
+    # against the tight-tolerance truth (the oracle at rtol 1e-12, atol 1e-20, fresh Newton matrices)
+    # on a sub-sample of at most 256 cells sized to about 45 s of host time; a truth cell costs about
+    # 8x a same-settings cell, 20x when the same-settings run kept its Newton matrices
+    per_cell_truth = el * threads / idx.size * (20.0 if args.jac_reuse else 8.0)
+    n_sub = int(min(256, idx.size, 45.0 * threads / per_cell_truth))
+    if n_sub < 4:
+        acc["vs_truth"] = {"cells": 0, "what": f"skipped: about {per_cell_truth:.0f} s per truth cell on one core"}
     else:
-        sub = idx[:: max(1, idx.size // 256)]
+        sub = idx[:: max(1, idx.size // n_sub)]
         pos = np.searchsorted(idx, sub)
         print(f"cpu baseline: truth reference on {sub.size} cells", file=sys.stderr, flush=True)
         Tt, Yt, _ = om.integrate(w.T[sub], w.Y[:, sub], w.p, w.dt, 1e-12, 1e-20, q_max=args.q_max,
@@ -268,7 +277,8 @@ def bench_boxes(args, torch, dev, chem, synth):
     m = synth.config_mechanism(4)
     boxes = synth.amr_boxes(m, args.n_boxes, synth.config_seed(4), max_cells=args.max_box_cells)
     gm = chem.Mechanism(m.to_text())
-    gm.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32), kernel=KERNEL_CODES[args.kernel])
+    gm.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32), kernel=KERNEL_CODES[args.kernel],
+                   jac_reuse=int(args.jac_reuse))
     src = [(torch.tensor(b.T, device=dev), torch.tensor(b.Y, device=dev), b.dt) for b in boxes]
     work = [(t.clone(), y.clone(), dt) for t, y, dt in src]
     sample_T = torch.cat([t[: min(256, t.numel())] for t, _, _ in src[:8]])
@@ -300,7 +310,8 @@ def bench_boxes(args, torch, dev, chem, synth):
         "box_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                            "what": "launch to box completion, host-observed"},
         "config": {"workload": f"{len(boxes)} boxes of G(30,180,4,seed 3), edges log-uniform 8..64 capped at "
-                               f"{args.max_box_cells} cells, per-box dt log-uniform 1e-7..1e-5 s, rtol 1e-8",
+                               f"{args.max_box_cells} cells, per-box dt log-uniform 1e-7..1e-5 s, rtol 1e-8, "
+                               + ("Newton matrix kept while recent" if args.jac_reuse else "fresh Newton matrix"),
                    "cells": n, "group_width": width, "waves_per_cu": waves},
         "integration": {"steps_per_cell": stats["n_steps_total"] / n, "failed_cells": stats["n_cells_failed"]},
     }), flush=True)

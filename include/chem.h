@@ -89,6 +89,11 @@ typedef struct {
                                    temperature column, as in Sec. 3.2.2 (one extra right-hand side).
                                    Increment of column j: max(sqrt(u)|y_j|, 1000 h u N ||f||_w / w_j),
                                    u the FP64 unit roundoff, w the error weights.  Group kernels only */
+#define CHEM_OPT_JAC_REUSE 12   /* 1: keep the factored Newton matrix M = I - cJ across attempts while c
+                                   is within 30% of the c it was formed with, fewer than 20 accepted
+                                   steps have passed and Newton has not failed with it (a failure
+                                   retries the step with a fresh Jacobian), as CVODE does; 0 (default):
+                                   a fresh Jacobian and LU every attempt */
 
 /* Parse a mechanism from a file path / from text (format "chem-mech 1":
  * elements with masses; species with atom counts, inert flag and linear

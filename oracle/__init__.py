@@ -168,7 +168,7 @@ class Mech:
     # -- whole-batch integration ---------------------------------------------
     def integrate(self, T: np.ndarray, Y: np.ndarray, p: float, dt: float, rtol: float, atol: float,
                   max_steps: int = 100000, q_max: int = 5, fixed_T: bool = False, fixed_step_n: int = 0,
-                  nthreads: int = 0, want_stats: bool = True, jac_mode: int = 0, jac_reuse: bool = True):
+                  nthreads: int = 0, want_stats: bool = True, jac_mode: int = 0, jac_reuse: bool = False):
         """Returns (T_out, Y_out, stats) where stats is a structured numpy array
         (one record per cell) or None.  Inputs are not modified."""
         T = np.array(T, dtype=np.float64, copy=True).ravel()

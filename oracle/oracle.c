@@ -483,7 +483,8 @@ typedef struct {
   int jac_mode;        /* Newton Jacobian: 0 analytic (Eq. 7), 1 difference quotients in every
                           column, 2 analytic species columns with a difference-quotient T column */
   int jac_reuse;       /* 1: keep the factored Newton matrix across attempts while it is recent
-                          (see orc_integrate_cell); 0: a fresh Jacobian and LU every attempt */
+                          (see orc_integrate_cell); 0 (the default reading): a fresh Jacobian and
+                          LU every attempt */
 } orc_opts;
 
 typedef struct {

@@ -39,7 +39,7 @@ struct chem_mech {
   int device = 0;
   int n_cu = 256;
   // options
-  int max_steps = 100000, q_max = 5, fixed_T = 0, fixed_step_n = 0, lu_fp32 = 0, ir_max = 3, jac_mode = 0;
+  int max_steps = 100000, q_max = 5, fixed_T = 0, fixed_step_n = 0, lu_fp32 = 0, ir_max = 3, jac_mode = 0, jac_reuse = 0;
   int use_graph = 1, waves_per_cu = 8;
   int kernel_mode = 0;           // 0 auto, 1 group kernels, 2 lane-per-cell kernels
   // lane-per-cell module (generated source, compiled on first use per device)
@@ -100,5 +100,6 @@ inline chemgpu::IntParams make_int_params(const chem_mech* m, double p, double d
   prm.lu_fp32 = m->lu_fp32;
   prm.ir_max = m->ir_max;
   prm.jac_mode = m->jac_mode;
+  prm.jac_reuse = m->jac_reuse;
   return prm;
 }

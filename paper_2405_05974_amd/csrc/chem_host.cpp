@@ -442,6 +442,9 @@ int chem_set_option(chem_mech* m, int key, double value) {
         return fail(CHEM_ERR_ARG, "jac must be 0 (analytic), 1 (difference quotients) or 2 (difference-quotient T column)");
       m->jac_mode = (int)v;
       return CHEM_OK;
+    case CHEM_OPT_JAC_REUSE:
+      m->jac_reuse = v != 0;
+      return CHEM_OK;
     case CHEM_OPT_KERNEL:
       if (v != 0 && v != 1 && v != 2) return fail(CHEM_ERR_ARG, "kernel must be 0 (auto), 1 (group) or 2 (lane per cell)");
       m->kernel_mode = (int)v;
@@ -489,6 +492,7 @@ int chem_integrate_ex(chem_mech* m, int64_t n_cells, double* T, double* Y, doubl
   prm.lu_fp32 = m->lu_fp32;
   prm.ir_max = m->ir_max;
   prm.jac_mode = m->jac_mode;
+  prm.jac_reuse = m->jac_reuse;
   bool lpc = false;
   const int krc = chem_select_kernel(m, &lpc);
   if (krc != CHEM_OK) return krc;
@@ -624,6 +628,7 @@ int chem_integrate_boxes(chem_mech* m, int n_boxes, const chem_box* boxes, doubl
     prm.lu_fp32 = m->lu_fp32;
     prm.ir_max = m->ir_max;
     prm.jac_mode = m->jac_mode;
+    prm.jac_reuse = m->jac_reuse;
     const int grid = (int)std::min<int64_t>(tiles, (int64_t)m->waves_per_cu * m->n_cu);
     const auto t0 = std::chrono::steady_clock::now();
     e = hipEventRecord(m->ev0, m->stream);

@@ -70,6 +70,7 @@ struct IntParams {
   int max_steps, q_max, fixed_T, fixed_step_n;
   int lu_fp32, ir_max;
   int jac_mode;   // 0 analytic Jacobian, 1 difference quotients, 2 analytic with a difference-quotient T column
+  int jac_reuse;  // 1: keep the factored Newton matrix while recent; 0: fresh every attempt
 };
 
 // Launchers (chem_kernels.hip).  All enqueue on `stream` and return the HIP

@@ -338,6 +338,7 @@ namespace {
 struct LpcParams {   // layout of ChParams in the generated source
   double p, dt, rtol, atol;
   int max_steps, q_max, fixed_T, fixed_step_n;
+  int jac_reuse, pad;
 };
 LpcParams lpc_params(const IntParams& prm) {
   LpcParams q;
@@ -349,6 +350,8 @@ LpcParams lpc_params(const IntParams& prm) {
   q.q_max = prm.q_max;
   q.fixed_T = prm.fixed_T;
   q.fixed_step_n = prm.fixed_step_n;
+  q.jac_reuse = prm.jac_reuse;
+  q.pad = 0;
   return q;
 }
 }  // namespace

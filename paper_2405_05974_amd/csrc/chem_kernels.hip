@@ -797,6 +797,13 @@ __device__ __forceinline__ void integrate_group(const DevMech& m, const IntParam
     D[1] = h * f;
     int k = 1, etf = 0, nk = 0;
     double t = 0.0;
+    // the factored Newton matrix (LDS rows, perm, rdiag) is kept across
+    // attempts while it is recent
+    bool have_lu = false, stale_fail = false;
+    int steps_lu = 0;
+    double c_lu = 0.0;
+    double rdiag = 0.0;
+    float rdiag32 = 0.0f;
     while (t < dt) {
       const int rl = opaque_lane() % NP;   // lane-index tests stay inside the loop
       if (attempts >= P.max_steps) {
@@ -830,20 +837,31 @@ __device__ __forceinline__ void integrate_group(const DevMech& m, const IntParam
       const double psi = ss / gk;
       const double c = h / gk;
 
-      double fp;
-      if (P.jac_mode == 1) {
-        // f(pred) serves the quotients and the first Newton residual
-        rhs_eval<NP, false>(m, sc, P.p, fixedT, pred, fp, wdx, sh);
-        nrhs += jac_difference_quotients<NP>(m, sc, P.p, fixedT, pred, fp, w, h, N, 0, sh);
-      } else {
-        rhs_eval<NP, true>(m, sc, P.p, fixedT, pred, fp, wdx, sh);
-        if (P.jac_mode == 2) nrhs += jac_difference_quotients<NP>(m, sc, P.p, fixedT, pred, fp, w, h, N, N - 1, sh);
+      // keep the factors while c is within 30% of the c they were formed with,
+      // fewer than 20 accepted steps have passed and Newton has not failed
+      // with them; otherwise a fresh Jacobian at the predictor (all of this
+      // is group-uniform)
+      const bool fresh = !P.jac_reuse || !have_lu || fabs(c / c_lu - 1.0) > 0.3 || steps - steps_lu >= 20 ||
+                         stale_fail;
+      double fp = 0.0;
+      if (fresh) {
+        if (P.jac_mode == 1) {
+          // f(pred) serves the quotients and the first Newton residual
+          rhs_eval<NP, false>(m, sc, P.p, fixedT, pred, fp, wdx, sh);
+          nrhs += jac_difference_quotients<NP>(m, sc, P.p, fixedT, pred, fp, w, h, N, 0, sh);
+        } else {
+          rhs_eval<NP, true>(m, sc, P.p, fixedT, pred, fp, wdx, sh);
+          if (P.jac_mode == 2)
+            nrhs += jac_difference_quotients<NP>(m, sc, P.p, fixedT, pred, fp, w, h, N, N - 1, sh);
+        }
+        njac++;
+        if constexpr (F32) factor_newton_matrix_f32<NP>(sh, c, rdiag32);
+        else factor_newton_matrix<NP>(sh, c, rdiag);
+        have_lu = true;
+        c_lu = c;
+        steps_lu = steps;
+        stale_fail = false;
       }
-      njac++;
-      double rdiag = 0.0;
-      float rdiag32 = 0.0f;
-      if constexpr (F32) factor_newton_matrix_f32<NP>(sh, c, rdiag32);
-      else factor_newton_matrix<NP>(sh, c, rdiag);
 
       double d = 0.0;
       bool conv = false;
@@ -852,7 +870,7 @@ __device__ __forceinline__ void integrate_group(const DevMech& m, const IntParam
       const double ntol = fixed ? 1e-10 : 0.03;
       for (int it = 1; it <= maxit; ++it) {
         double fi;
-        if (it == 1) {
+        if (it == 1 && fresh) {
           fi = fp;   // f at pred + 0 was evaluated with the Jacobian
         } else {
           rhs_eval<NP, false>(m, sc, P.p, fixedT, pred + d, fi, wdx, sh);
@@ -871,6 +889,11 @@ __device__ __forceinline__ void integrate_group(const DevMech& m, const IntParam
         }
         if (it > 1 && nrm > 2.0 * prev) break;
         prev = nrm;
+      }
+      if (!conv && !fixed && !fresh) {   // kept factors failed: same step, fresh matrix
+        nnnf++;
+        stale_fail = true;
+        continue;
       }
       if (!conv && !fixed) {
         nnnf++;

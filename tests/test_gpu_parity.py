@@ -342,6 +342,48 @@ def test_difference_quotient_jacobian_parity(chem, torch_dev, mode):
     assert dY <= TOL_FD_Y and dT <= TOL_FD_T
 
 
+# Kept Newton matrices (CHEM_OPT_JAC_REUSE) make Newton converge linearly, so
+# its stopping iterate sits anywhere inside the 0.03 WRMS tolerance and
+# rounding differences can move the stop by one iteration; later decisions
+# then differ.  Results agree to the integration accuracy: the oracle's own
+# kept-matrix runs are within 9e-8 (T) of the tight truth on config-1 cells.
+TOL_REUSE_Y = 1e-7
+TOL_REUSE_T = 2e-7
+
+
+@KERNELS
+def test_newton_matrix_reuse_parity(chem, torch_dev, kernel):
+    """CVODE's Newton-matrix policy (factors kept while c stays within 30%,
+    at most 20 steps, refreshed after a Newton failure) against the oracle's
+    same option, on all config-1 cells and a config-2 flame sample."""
+    w = synth.config_workload(1)
+    text = w.mech.to_text()
+    say(f"jac_reuse config1 n={w.n_cells} kernel={kernel}")
+    Tg, Yg, st, rec = gpu_integrate(chem, torch_dev, text, w.T, w.Y, w.p, w.dt, w.rtol, w.atol, kernel=kernel,
+                                    jac_reuse=1)
+    To, Yo, so = oracle_integrate(text, w.T, w.Y, w.p, w.dt, w.rtol, w.atol, jac_reuse=True)
+    assert st["rc"] == 0 and (rec[0] == 0).all()
+    dY = np.abs(Yg - Yo).max()
+    dT = (np.abs(Tg - To) / To).max()
+    say(f"jac_reuse config1: max|dY|={dY:.3e} max|dT|/T={dT:.3e}; jacobians {st['n_jac']} of "
+        f"{st['n_attempts']} attempts (oracle {so['n_jac'].sum()} of {so['attempts'].sum()})")
+    assert dY <= TOL_REUSE_Y and dT <= TOL_REUSE_T
+    assert st["n_jac"] < 0.3 * st["n_attempts"]
+    assert abs(st["n_jac"] / so["n_jac"].sum() - 1) <= 0.05
+    assert abs(rec[1].sum() / so["steps"].sum() - 1) <= 0.02
+    w2 = synth.config_workload(2, GOLDEN, shape=(256, 2, 2))
+    text2 = w2.mech.to_text()
+    say(f"jac_reuse flame sample n={w2.n_cells} kernel={kernel}")
+    Tg, Yg, st, rec = gpu_integrate(chem, torch_dev, text2, w2.T, w2.Y, w2.p, w2.dt, w2.rtol, w2.atol,
+                                    kernel=kernel, jac_reuse=1)
+    To, Yo, so = oracle_integrate(text2, w2.T, w2.Y, w2.p, w2.dt, w2.rtol, w2.atol, jac_reuse=True)
+    dY = np.abs(Yg - Yo).max()
+    dT = (np.abs(Tg - To) / To).max()
+    say(f"jac_reuse flame sample: max|dY|={dY:.3e} max|dT|/T={dT:.3e}; jacobians {st['n_jac']} of "
+        f"{st['n_attempts']} attempts")
+    assert st["rc"] == 0 and dY <= TOL_REUSE_Y and dT <= TOL_REUSE_T
+
+
 def test_config3_sample(chem, torch_dev):
     w = synth.config_workload(3, GOLDEN, shape=(256, 1, 1))
     idx = np.arange(0, 256, 16)

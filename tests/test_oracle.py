@@ -426,15 +426,17 @@ def test_integration_against_tight_reference(g10, g10_run):
 
 
 def test_newton_matrix_reuse(g10, g10_run):
-    """Keeping the factored Newton matrix while it is recent (the default)
+    """Keeping the factored Newton matrix while it is recent (the option)
     changes how Newton converges, not what it converges to: the result stays
     within a small multiple of rtol of the truth, like the fresh-every-attempt
-    run, while most attempts skip the Jacobian and the factorisation."""
+    run (the default), while most attempts skip the Jacobian and the
+    factorisation."""
     m, om = g10
-    w, T, Y, st = g10_run
+    w, Tf0, Yf0, sf0 = g10_run
     idx = np.arange(0, 48, 3)
-    Tt, Yt, _ = om.integrate(w.T[idx], w.Y[:, idx], w.p, w.dt, 1e-12, 1e-20, jac_reuse=False)
-    Tf, Yf, sf = om.integrate(w.T[idx], w.Y[:, idx], w.p, w.dt, w.rtol, w.atol, jac_reuse=False)
+    Tt, Yt, _ = om.integrate(w.T[idx], w.Y[:, idx], w.p, w.dt, 1e-12, 1e-20)
+    T, Y, st = om.integrate(w.T, w.Y, w.p, w.dt, w.rtol, w.atol, jac_reuse=True)
+    Tf, Yf, sf = Tf0[idx], Yf0[:, idx], sf0[idx]
     assert (sf["n_jac"] == sf["attempts"]).all()
     for Ta, Ya in ((T[idx], Y[:, idx]), (Tf, Yf)):
         assert np.abs(Ya - Yt).max() <= 1e-7
