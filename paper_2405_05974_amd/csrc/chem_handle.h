@@ -48,6 +48,7 @@ struct chem_mech {
   void* lpc_integrate = nullptr;
   void* lpc_boxes = nullptr;
   int lpc_device = -1;
+  int lpc_reuse = -1;   // CH_REUSE of the loaded module
   // workspace
   int32_t* rec = nullptr;
   int64_t rec_cap = 0;
@@ -69,7 +70,7 @@ struct chem_mech {
 };
 
 namespace chemgpu {
-std::string lpc_source(const HostMech& m);
+std::string lpc_source(const HostMech& m, bool reuse);
 int lpc_module(const std::string& src, int device, void** integrate_fn, void** boxes_fn, std::string& log);
 }  // namespace chemgpu
 

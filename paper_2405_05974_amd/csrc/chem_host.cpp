@@ -330,12 +330,14 @@ int chem_select_kernel(chem_mech* m, bool* lpc) {
   *lpc = want;
   if (!want) return CHEM_OK;
   std::lock_guard<std::mutex> lk(m->lpc_mu);
-  if (m->lpc_integrate && m->lpc_device == m->device) return CHEM_OK;
-  if (m->lpc_src.empty()) m->lpc_src = chemgpu::lpc_source(m->host);
+  const int reuse = m->jac_reuse ? 1 : 0;
+  if (m->lpc_integrate && m->lpc_device == m->device && m->lpc_reuse == reuse) return CHEM_OK;
+  if (m->lpc_src.empty() || m->lpc_reuse != reuse) m->lpc_src = chemgpu::lpc_source(m->host, reuse != 0);
   std::string log;
   if (chemgpu::lpc_module(m->lpc_src, m->device, &m->lpc_integrate, &m->lpc_boxes, log) != 0)
     return fail(CHEM_ERR_DEVICE, log);
   m->lpc_device = m->device;
+  m->lpc_reuse = reuse;
   return CHEM_OK;
 }
 

@@ -63,7 +63,7 @@ void emit_nu_update(std::ostringstream& o, const char* arr, int k, int nu, const
 
 }  // namespace
 
-std::string lpc_source(const HostMech& m) {
+std::string lpc_source(const HostMech& m, bool reuse) {
   const int S = (int)m.W.size(), R = (int)m.rx.size(), N = S + 1;
   // Mechanism parameters are read from a __constant__ table (scalar loads,
   // several constants per instruction) rather than written as literals, each
@@ -257,6 +257,9 @@ std::string lpc_source(const HostMech& m) {
   head << "// generated: lane-per-cell kernels for a mechanism with " << S << " species and " << R
        << " reactions\n";
   head << "#define CH_S " << S << "\n#define CH_N " << N << "\n";
+  // Newton-matrix reuse is compiled in only when asked for: keeping the
+  // factors across attempts holds them in registers through the whole step
+  head << "#define CH_REUSE " << (reuse ? 1 : 0) << "\n";
   head << "#define CH_RU " << lit(kRu) << "\n#define CH_RU_CGS " << lit(kRuCgs) << "\n#define CH_PATM "
        << lit(kPatm) << "\n#define CH_TREF " << lit(kTref) << "\n";
   head << "__constant__ double ch_K[" << std::max<size_t>(pool.size(), 1) << "] = {";
