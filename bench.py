@@ -321,8 +321,8 @@ def bench_jacstudy(args, torch, dev, chem, synth):
     """The paper's analytic-vs-finite-difference Jacobian comparison (Sec. 3.2,
     the speedup column of its Table 4) on the GPU: the same cells integrated
     by the group kernels with the analytic Jacobian, with difference quotients
-    in every column, and with only the temperature column by differences
-    (Sec. 3.2.2).  Mechanisms G(10,25,3), G(30,180,4), G(53,325,4); flame-box
+    in every column, with only the temperature column by differences
+    (Sec. 3.2.2), and with the analytic Jacobian and kept Newton matrices.  Mechanisms G(10,25,3), G(30,180,4), G(53,325,4); flame-box
     states for S = 10 and 53, AMR-box states for S = 30.  One timed call per
     (mechanism, mode) after a warm-up call."""
     golden = os.path.join(ROOT, "tests", "golden")
@@ -343,8 +343,8 @@ def bench_jacstudy(args, torch, dev, chem, synth):
         Y0 = torch.tensor(np.ascontiguousarray(Y0n, dtype=np.float64), device=dev)
         row = {"mechanism": name, "species": m.n_species, "reactions": m.n_reactions, "cells": int(T0.numel()),
                "states": what, "dt": dt, "rtol": rtol}
-        for mode, key in ((0, "analytic"), (1, "fd"), (2, "fd_T")):
-            gm.set_options(q_max=args.q_max, kernel=KERNEL_CODES["group"], jac=mode)
+        for mode, key, reuse in ((0, "analytic", 0), (1, "fd", 0), (2, "fd_T", 0), (0, "analytic_kept", 1)):
+            gm.set_options(q_max=args.q_max, kernel=KERNEL_CODES["group"], jac=mode, jac_reuse=reuse)
             T, Y = T0.clone(), Y0.clone()
             gm.integrate(T, Y, synth.P_ATM, dt, rtol, atol)                       # warm-up
             T.copy_(T0)
@@ -352,11 +352,13 @@ def bench_jacstudy(args, torch, dev, chem, synth):
             st = gm.integrate(T, Y, synth.P_ATM, dt, rtol, atol)
             n = T0.numel()
             row[key] = {"kernel_ms": st["wall_ms"], "steps_per_cell": st["n_steps_total"] / n,
+                        "jacobians_per_cell": st["n_jac"] / n,
                         "rhs_per_cell": st["n_rhs"] / n, "newton_per_cell": st["n_newton_iters"] / n,
                         "failed_cells": st["n_cells_failed"]}
             print(f"jacstudy {name} {key}: {st['wall_ms']:.1f} ms", file=sys.stderr, flush=True)
         row["speedup_analytic_vs_fd"] = row["fd"]["kernel_ms"] / row["analytic"]["kernel_ms"]
         row["speedup_analytic_vs_fd_T"] = row["fd_T"]["kernel_ms"] / row["analytic"]["kernel_ms"]
+        row["speedup_kept_matrix_vs_analytic"] = row["analytic"]["kernel_ms"] / row["analytic_kept"]["kernel_ms"]
         rows.append(row)
     print(json.dumps({"mode": "jacstudy", "dtype": "f64", "data": "synthetic", "kernel": "group kernels",
                       "rows": rows}), flush=True)
