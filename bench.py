@@ -371,7 +371,7 @@ def bench_serve(args, torch, dev, chem, synth):
     mechs_ = [synth.config_mechanism(2), synth.config_mechanism(3)]
     handles = [chem.Mechanism(m.to_text()) for m in mechs_]
     for h in handles:
-        h.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32),
+        h.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32), jac_reuse=int(args.jac_reuse),
                       kernel=KERNEL_CODES[args.kernel] if h.N <= LANE_MAX_N or args.kernel != "lane" else 0)
     arrivals = synth.poisson_trace(1005, args.rate, args.duration)
     rng = np.random.default_rng(1005)
