@@ -235,7 +235,8 @@ def cpu_baseline(w, Tg, Yg, args):
     acc = {"vs": "CPU oracle, same inputs and settings", "cells": int(idx.size),
            "max_abs_dY": float(np.abs(Ygs - Yo).max()),
            "max_rel_dT": float((np.abs(Tgs - To) / To).max()),
-           "p99_abs_dY": float(np.percentile(np.abs(Ygs - Yo).max(axis=0), 99))}
+           "p99_abs_dY": float(np.percentile(np.abs(Ygs - Yo).max(axis=0), 99)),
+           "p99_rel_dT": float(np.percentile(np.abs(Tgs - To) / To, 99))}
     # against the tight-tolerance truth (the oracle at rtol 1e-12, atol 1e-20, fresh Newton matrices)
     # on a sub-sample of at most 256 cells sized to about 45 s of host time; a truth cell costs about
     # 8x a same-settings cell, 20x when the same-settings run kept its Newton matrices
@@ -253,8 +254,26 @@ def cpu_baseline(w, Tg, Yg, args):
                            "max_rel_dT_gpu": float((np.abs(Tgs[pos] - Tt) / Tt).max()),
                            "max_abs_dY_oracle": float(np.abs(Yo[:, pos] - Yt).max()),
                            "what": "truth = the oracle at rtol 1e-12, atol 1e-20"}
+    # one core on a sub-sample of about 5 s
+    n1 = int(max(1, min(idx.size, 5.0 * idx.size / (el * threads))))
+    sub1 = idx[:: max(1, idx.size // n1)]
+    t1 = time.perf_counter()
+    om.integrate(w.T[sub1], w.Y[:, sub1], w.p, w.dt, w.rtol, w.atol, q_max=args.q_max, nthreads=1,
+                 jac_reuse=args.jac_reuse, want_stats=False)
+    el1 = time.perf_counter() - t1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     base = {"value": idx.size / el, "unit": "cells/s", "cores": threads, "kind": "oracle",
-            "sample": f"{idx.size} cells evenly strided over the {n}-cell box ({el:.1f} s)"}
+            "sample": f"{idx.size} cells evenly strided over the {n}-cell box ({el:.1f} s)",
+            "one_core": {"value": sub1.size / el1, "cells": int(sub1.size), "seconds": el1},
+            "cpu_model": model}
     return base, acc
 
 

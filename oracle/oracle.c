@@ -829,7 +829,7 @@ int64_t orc_integrate(const orc_mech *m, int64_t n, double *T, double *Y, double
 #else
   (void)nthreads;
 #endif
-#pragma omp parallel for schedule(dynamic, 64) reduction(+ : failed)
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : failed)
   for (int64_t i = 0; i < n; ++i) {
     double y[1025];
     orc_cell_stats st;
