@@ -441,6 +441,33 @@ def test_boxes_batch_equals_alone_and_oracle(chem, torch_dev, width):
             assert_parity(Tg, Yg, To, Yo, f"box {i}")
 
 
+@KERNELS
+def test_boxes_with_kept_newton_matrices(chem, torch_dev, kernel):
+    """The persistent box queue with kept Newton matrices: each box batched
+    equals the box alone bit for bit (the kept factors belong to one cell),
+    and matches the oracle's same option to the kept-matrix bar."""
+    torch, dev = torch_dev
+    m = synth.config_mechanism(1 if kernel == 2 else 4)
+    text = m.to_text()
+    bxs = _boxes(m, 5, 2024, 40)
+    say(f"kept-matrix boxes kernel={kernel} cells={[b.T.size for b in bxs]}")
+    gm = chem.Mechanism(text)
+    gm.set_options(kernel=kernel, jac_reuse=1)
+    tens = [(torch.tensor(b.T, device=dev), torch.tensor(b.Y, device=dev), b.dt) for b in bxs]
+    st, _ = gm.integrate_boxes(tens, synth.P_ATM, 1e-8, 1e-12)
+    torch.cuda.synchronize()
+    assert st["rc"] == 0 and st["n_jac"] < 0.5 * st["n_attempts"]
+    for i, b in enumerate(bxs[:3]):
+        Tg, Yg, _, _ = gpu_integrate(chem, torch_dev, text, b.T, b.Y, synth.P_ATM, b.dt, 1e-8, 1e-12,
+                                     kernel=kernel, jac_reuse=1)
+        assert np.array_equal(tens[i][0].cpu().numpy(), Tg) and np.array_equal(tens[i][1].cpu().numpy(), Yg)
+        To, Yo, _ = oracle_integrate(text, b.T, b.Y, synth.P_ATM, b.dt, 1e-8, 1e-12, jac_reuse=True)
+        dY = np.abs(Yg - Yo).max()
+        dT = (np.abs(Tg - To) / To).max()
+        say(f"kept-matrix box {i}: max|dY|={dY:.3e} max|dT|/T={dT:.3e}")
+        assert dY <= TOL_REUSE_Y and dT <= TOL_REUSE_T
+
+
 def test_boxes_graph_replay_matches_direct(chem, torch_dev):
     torch, dev = torch_dev
     m = synth.config_mechanism(1)
@@ -472,6 +499,13 @@ def test_fp32_lu_refined_matches_fp64(chem, torch_dev):
     dT = (np.abs(Tg - To) / To).max()
     say(f"lu_fp32: max|dY|={dY:.3e} max|dT|/T={dT:.3e}")
     assert dY <= 1e-6 and dT <= 1e-6
+    # with kept Newton matrices the refinement residual uses the kept Jacobian at the current c
+    Tg, Yg, st, rec = gpu_integrate(chem, torch_dev, text, w.T, w.Y, w.p, 2e-6, 1e-6, 1e-12, lu_fp32=1, jac_reuse=1)
+    dY = np.abs(Yg - Yo).max()
+    dT = (np.abs(Tg - To) / To).max()
+    say(f"lu_fp32 with kept matrices: max|dY|={dY:.3e} max|dT|/T={dT:.3e}; jacobians {st['n_jac']} of "
+        f"{st['n_attempts']}")
+    assert st["rc"] == 0 and dY <= 1e-5 and dT <= 1e-5
 
 
 # ------------------------------------------------------------------ serving
