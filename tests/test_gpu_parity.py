@@ -384,6 +384,26 @@ def test_newton_matrix_reuse_parity(chem, torch_dev, kernel):
     assert st["rc"] == 0 and dY <= TOL_REUSE_Y and dT <= TOL_REUSE_T
 
 
+@pytest.mark.parametrize("S,R,E,dt,T_lo,T_hi", [
+    (11, 30, 3, 1e-7, 1000.0, 1600.0),     # N = 12, the largest lane-per-cell size
+    (15, 40, 3, 1e-7, 1000.0, 1600.0),     # N = 16 fills a 16-lane group: no padding rows
+    (31, 90, 4, 1e-7, 1000.0, 1600.0),     # N = 32 fills a 32-lane group
+    (63, 150, 4, 1e-8, 1800.0, 2200.0),    # N = 64, the largest mechanism: a full wave per cell
+], ids=["N12", "N16", "N32", "N64"])
+def test_full_width_mechanisms(chem, torch_dev, S, R, E, dt, T_lo, T_hi):
+    """Generated mechanisms whose state exactly fills a group width (no
+    padding lanes or rows) and the largest lane-per-cell size, through the
+    automatic kernel choice, against the oracle."""
+    m = synth.make_mechanism(S, R, E, 77)
+    w = synth.uniform_batch(m, 16, 5, T_lo, T_hi, dt, 1e-8, 1e-12)
+    text = m.to_text()
+    say(f"full-width mechanism S={S} R={R} n={w.n_cells} dt={dt:g}")
+    Tg, Yg, st, rec = gpu_integrate(chem, torch_dev, text, w.T, w.Y, w.p, w.dt, w.rtol, w.atol)
+    To, Yo, so = oracle_integrate(text, w.T, w.Y, w.p, w.dt, w.rtol, w.atol)
+    assert st["rc"] == 0 and (rec[0] == 0).all() and (so["status"] == 0).all()
+    assert_parity(Tg, Yg, To, Yo, f"S={S}")
+
+
 def test_config3_sample(chem, torch_dev):
     w = synth.config_workload(3, GOLDEN, shape=(256, 1, 1))
     idx = np.arange(0, 256, 16)
