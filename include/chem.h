@@ -89,6 +89,13 @@ typedef struct {
                                    temperature column, as in Sec. 3.2.2 (one extra right-hand side).
                                    Increment of column j: max(sqrt(u)|y_j|, 1000 h u N ||f||_w / w_j),
                                    u the FP64 unit roundoff, w the error weights.  Group kernels only */
+#define CHEM_OPT_RETRY 13       /* k > 0: chem_integrate(_ex) integrates every cell that failed (attempt
+                                   limit or step-size underflow) again from its input state with dt split
+                                   into 2, 4, ... 2^k equal substeps, until one level passes every
+                                   substep (the paper's smaller-timestep restart, per cell); such cells
+                                   get that state and status 0, counters include the retry work, and the
+                                   stats are recomputed.  Keeps a device copy of the input state
+                                   (16(S+1) bytes per cell); wall_ms times the first pass.  Default 0 */
 #define CHEM_OPT_JAC_REUSE 12   /* 1: keep the factored Newton matrix M = I - cJ across attempts while c
                                    is within 30% of the c it was formed with, fewer than 20 accepted
                                    steps have passed and Newton has not failed with it (a failure

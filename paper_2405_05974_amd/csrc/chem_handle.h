@@ -40,6 +40,9 @@ struct chem_mech {
   int n_cu = 256;
   // options
   int max_steps = 100000, q_max = 5, fixed_T = 0, fixed_step_n = 0, lu_fp32 = 0, ir_max = 3, jac_mode = 0, jac_reuse = 0;
+  int retry = 0;                 // halvings of dt tried for failed cells (0: none)
+  double* retry_in = nullptr;    // the call's input state [T | Y], kept for retries
+  int64_t retry_cap = 0;
   int use_graph = 1, waves_per_cu = 8;
   int kernel_mode = 0;           // 0 auto, 1 group kernels, 2 lane-per-cell kernels
   // lane-per-cell module (generated source, compiled on first use per device)

@@ -378,6 +378,7 @@ void chem_mech_free(chem_mech* m) {
   if (!m) return;
   if (m->blob) (void)hipFree(m->blob);
   if (m->rec) (void)hipFree(m->rec);
+  if (m->retry_in) (void)hipFree(m->retry_in);
   if (m->dstats) (void)hipFree(m->dstats);
   if (m->ev0) (void)hipEventDestroy(m->ev0);
   if (m->ev1) (void)hipEventDestroy(m->ev1);
@@ -444,6 +445,10 @@ int chem_set_option(chem_mech* m, int key, double value) {
         return fail(CHEM_ERR_ARG, "jac must be 0 (analytic), 1 (difference quotients) or 2 (difference-quotient T column)");
       m->jac_mode = (int)v;
       return CHEM_OK;
+    case CHEM_OPT_RETRY:
+      if (v < 0 || v > 12) return fail(CHEM_ERR_ARG, "retry must be 0..12 halvings");
+      m->retry = (int)v;
+      return CHEM_OK;
     case CHEM_OPT_JAC_REUSE:
       m->jac_reuse = v != 0;
       return CHEM_OK;
@@ -463,6 +468,115 @@ int chem_set_option(chem_mech* m, int key, double value) {
       return fail(CHEM_ERR_ARG, "unknown option key " + std::to_string(key));
   }
 }
+
+namespace {
+
+hipError_t launch_either(chem_mech* m, bool lpc, const IntParams& prm, double* T, double* Y, int64_t n, int32_t* rec) {
+  if (lpc) return chemgpu::launch_lpc_integrate(m->lpc_integrate, prm, T, Y, n, rec, m->stream);
+  return chemgpu::launch_integrate(m->dev, prm, T, Y, n, rec, m->stream);
+}
+
+// The paper's remedy for a failed chemistry step, applied per cell: a cell
+// that failed (attempt limit or step-size underflow) is integrated again from
+// its input state with dt split into 2, 4, ... 2^retry equal substeps, until
+// one level passes every substep.  Passed cells get that state and status 0;
+// every cell's counters include the retry work.  The gather and scatter run
+// on the host: they only happen when cells failed.
+int retry_failed_cells(chem_mech* m, const IntParams& prm, bool lpc, int64_t n, double* T, double* Y, int32_t* rec,
+                       unsigned long long* hs) {
+  const int S = m->dev.S, N = S + 1, rows = chemgpu::kRecRows;
+  std::vector<int32_t> hrec((size_t)rows * n);
+  hipError_t e = hipMemcpy(hrec.data(), rec, sizeof(int32_t) * hrec.size(), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "retry: records");
+  std::vector<int64_t> idx;
+  for (int64_t i = 0; i < n; ++i)
+    if (hrec[i] == 1 || hrec[i] == 2) idx.push_back(i);
+  if (idx.empty()) return CHEM_OK;
+  const int64_t mc = (int64_t)idx.size();
+  std::vector<double> hin((size_t)N * n);
+  e = hipMemcpy(hin.data(), m->retry_in, sizeof(double) * hin.size(), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "retry: saved inputs");
+  std::vector<char> done(mc, 0);
+  std::vector<double> result((size_t)N * mc, 0.0);
+  std::vector<int32_t> acc((size_t)rows * mc, 0);
+  double* dwork = nullptr;
+  int32_t* drec = nullptr;
+  e = hipMalloc(&dwork, sizeof(double) * N * mc);
+  if (e == hipSuccess) e = hipMalloc(&drec, sizeof(int32_t) * rows * mc);
+  if (e != hipSuccess) {
+    (void)hipFree(dwork);
+    return fail(CHEM_ERR_OOM, "retry: device buffers");
+  }
+  int rc = CHEM_OK;
+  for (int level = 1; level <= m->retry && rc == CHEM_OK; ++level) {
+    std::vector<int64_t> todo;
+    for (int64_t j = 0; j < mc; ++j)
+      if (!done[j]) todo.push_back(j);
+    if (todo.empty()) break;
+    const int64_t mt = (int64_t)todo.size();
+    std::vector<double> w((size_t)N * mt);
+    for (int64_t t = 0; t < mt; ++t) {
+      const int64_t i = idx[todo[t]];
+      w[t] = hin[i];
+      for (int k = 0; k < S; ++k) w[mt + (size_t)k * mt + t] = hin[n + (size_t)k * n + i];
+    }
+    e = hipMemcpy(dwork, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { rc = hip_fail(e, "retry: upload"); break; }
+    const int nsub = 1 << level;
+    IntParams q = prm;
+    q.dt = prm.dt / nsub;
+    std::vector<char> ok(mt, 1);
+    std::vector<int32_t> hr((size_t)rows * mt);
+    for (int s = 0; s < nsub; ++s) {
+      e = launch_either(m, lpc, q, dwork, dwork + mt, mt, drec);
+      if (e == hipSuccess) e = hipMemcpyAsync(hr.data(), drec, sizeof(int32_t) * hr.size(), hipMemcpyDeviceToHost, m->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+      if (e != hipSuccess) { rc = hip_fail(e, "retry: substep"); break; }
+      for (int64_t t = 0; t < mt; ++t) {
+        if (hr[t] != 0) ok[t] = 0;
+        for (int r = 1; r < rows; ++r) acc[(size_t)r * mc + todo[t]] += hr[(size_t)r * mt + t];
+      }
+    }
+    if (rc != CHEM_OK) break;
+    e = hipMemcpy(w.data(), dwork, sizeof(double) * w.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) { rc = hip_fail(e, "retry: download"); break; }
+    for (int64_t t = 0; t < mt; ++t) {
+      if (!ok[t]) continue;
+      const int64_t j = todo[t];
+      done[j] = 1;
+      result[j] = w[t];
+      for (int k = 0; k < S; ++k) result[mc + (size_t)k * mc + j] = w[mt + (size_t)k * mt + t];
+    }
+  }
+  (void)hipFree(dwork);
+  (void)hipFree(drec);
+  if (rc != CHEM_OK) return rc;
+  std::vector<double> hT(n), hY((size_t)S * n);
+  e = hipMemcpy(hT.data(), T, sizeof(double) * n, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(hY.data(), Y, sizeof(double) * hY.size(), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "retry: state");
+  for (int64_t j = 0; j < mc; ++j) {
+    const int64_t i = idx[j];
+    if (done[j]) {
+      hT[i] = result[j];
+      for (int k = 0; k < S; ++k) hY[(size_t)k * n + i] = result[mc + (size_t)k * mc + j];
+      hrec[i] = 0;
+    }
+    for (int r = 1; r < rows; ++r) hrec[(size_t)r * n + i] += acc[(size_t)r * mc + j];
+  }
+  e = hipMemcpy(T, hT.data(), sizeof(double) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(Y, hY.data(), sizeof(double) * hY.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(rec, hrec.data(), sizeof(int32_t) * hrec.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = chemgpu::launch_reduce_records(rec, n, m->dstats, m->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hs, m->dstats, sizeof(unsigned long long) * chemgpu::kStatCount, hipMemcpyDeviceToHost,
+                       m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  if (e != hipSuccess) return hip_fail(e, "retry: write-back");
+  return CHEM_OK;
+}
+
+}  // namespace
 
 int chem_integrate_ex(chem_mech* m, int64_t n_cells, double* T, double* Y, double p, double dt, double rtol,
                       double atol, chem_stats* stats, int32_t* cell_records) {
@@ -498,10 +612,26 @@ int chem_integrate_ex(chem_mech* m, int64_t n_cells, double* T, double* Y, doubl
   bool lpc = false;
   const int krc = chem_select_kernel(m, &lpc);
   if (krc != CHEM_OK) return krc;
-  hipError_t e = hipEventRecord(m->ev0, m->stream);
+  hipError_t e = hipSuccess;
+  const int N = m->dev.S + 1;
+  if (m->retry > 0) {   // keep the input state for cells that may need a retry
+    if (m->retry_cap < n_cells) {
+      if (m->retry_in) (void)hipFree(m->retry_in);
+      m->retry_in = nullptr;
+      m->retry_cap = 0;
+      e = hipMalloc(&m->retry_in, sizeof(double) * N * n_cells);
+      if (e != hipSuccess) return fail(CHEM_ERR_OOM, "hipMalloc of the retry copy");
+      m->retry_cap = n_cells;
+    }
+    e = hipMemcpyAsync(m->retry_in, T, sizeof(double) * n_cells, hipMemcpyDeviceToDevice, m->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(m->retry_in + n_cells, Y, sizeof(double) * (N - 1) * n_cells, hipMemcpyDeviceToDevice,
+                         m->stream);
+    if (e != hipSuccess) return hip_fail(e, "retry copy");
+  }
+  e = hipEventRecord(m->ev0, m->stream);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-  if (lpc) e = chemgpu::launch_lpc_integrate(m->lpc_integrate, prm, T, Y, n_cells, rec, m->stream);
-  else e = chemgpu::launch_integrate(m->dev, prm, T, Y, n_cells, rec, m->stream);
+  e = launch_either(m, lpc, prm, T, Y, n_cells, rec);
   if (e != hipSuccess) return hip_fail(e, "integrate kernel launch");
   e = hipEventRecord(m->ev1, m->stream);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -514,6 +644,10 @@ int chem_integrate_ex(chem_mech* m, int64_t n_cells, double* T, double* Y, doubl
   if (e != hipSuccess) return hip_fail(e, "integrate");
   float ms = 0.0f;
   (void)hipEventElapsedTime(&ms, m->ev0, m->ev1);
+  if (hs[8] && m->retry > 0) {
+    const int rrc = retry_failed_cells(m, prm, lpc, n_cells, T, Y, rec, hs);
+    if (rrc != CHEM_OK) return rrc;
+  }
   if (stats) fill_stats(stats, n_cells, hs, ms);
   g_last_error.clear();
   return hs[8] ? CHEM_WARN_CELLS_FAILED : CHEM_OK;

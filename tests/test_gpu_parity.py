@@ -404,6 +404,57 @@ def test_full_width_mechanisms(chem, torch_dev, S, R, E, dt, T_lo, T_hi):
     assert_parity(Tg, Yg, To, Yo, f"S={S}")
 
 
+def _oracle_with_retries(text, T, Y, p, dt, rtol, atol, max_steps, levels):
+    """The retry policy written out on the oracle: cells that fail are
+    integrated again from their input with 2, 4, ... 2^levels substeps."""
+    import oracle
+    om = oracle.Mech(text)
+    To, Yo, so = om.integrate(T, Y, p, dt, rtol, atol, max_steps=max_steps)
+    status = so["status"].copy()
+    todo = np.where((status == 1) | (status == 2))[0]
+    for level in range(1, levels + 1):
+        if todo.size == 0:
+            break
+        Tc, Yc = T[todo].copy(), Y[:, todo].copy()
+        ok = np.ones(todo.size, bool)
+        for _ in range(2 ** level):
+            Tc, Yc, sc = om.integrate(Tc, Yc, p, dt / 2 ** level, rtol, atol, max_steps=max_steps)
+            ok &= sc["status"] == 0
+        To[todo[ok]] = Tc[ok]
+        Yo[:, todo[ok]] = Yc[:, ok]
+        status[todo[ok]] = 0
+        todo = todo[~ok]
+    return To, Yo, status
+
+
+@KERNELS
+def test_failed_cells_retried_with_substeps(chem, torch_dev, kernel):
+    """CHEM_OPT_RETRY: cells that hit the attempt limit are integrated again
+    from their input with dt halved until every substep passes; the result
+    matches the same policy written out on the oracle.  On these cells the
+    initial transient takes most of the steps, so only some are rescued: with
+    the attempt limit at the median need, 32 of 64 fail and 2 pass on retry."""
+    w = synth.config_workload(1)
+    idx = np.arange(0, w.n_cells, 64)
+    text = w.mech.to_text()
+    T, Y = w.T[idx], np.ascontiguousarray(w.Y[:, idx])
+    dt, max_steps, levels = 1e-4, 1074, 3
+    say(f"retry: n={idx.size} dt={dt} max_steps={max_steps} levels={levels} kernel={kernel}")
+    Tg, Yg, st, rec = gpu_integrate(chem, torch_dev, text, T, Y, w.p, dt, w.rtol, w.atol, kernel=kernel,
+                                    max_steps=max_steps, retry=levels)
+    To, Yo, status = _oracle_with_retries(text, T, Y, w.p, dt, w.rtol, w.atol, max_steps, levels)
+    Tg1, Yg1, st1, rec1 = gpu_integrate(chem, torch_dev, text, T, Y, w.p, dt, w.rtol, w.atol, kernel=kernel,
+                                        max_steps=max_steps)
+    say(f"retry: oracle {int((status == 0).sum())} of {idx.size} pass; gpu {int((rec[0] == 0).sum())} "
+        f"(without retry {int((rec1[0] == 0).sum())}); stats failed {st['n_cells_failed']}")
+    assert (rec[0] == status).mean() >= 0.95
+    assert st["n_cells_failed"] == int((rec[0] != 0).sum()) < st1["n_cells_failed"]
+    assert (rec[1] >= rec1[1]).all()          # counters include the retry work
+    both = (rec[0] == 0) & (status == 0)
+    assert both.sum() > 0
+    assert_parity(Tg[both], Yg[:, both], To[both], Yo[:, both], "retry")
+
+
 def test_config3_sample(chem, torch_dev):
     w = synth.config_workload(3, GOLDEN, shape=(256, 1, 1))
     idx = np.arange(0, 256, 16)
