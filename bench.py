@@ -62,11 +62,12 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16384, help="cells in the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--q-max", type=int, default=5)
-    ap.add_argument("--mode", choices=["flame", "boxes", "serve", "copy", "jacstudy"], default="flame",
+    ap.add_argument("--mode", choices=["flame", "boxes", "serve", "copy", "jacstudy", "sweep"], default="flame",
                     help="flame: the headline box; boxes: uneven AMR boxes in one persistent launch; "
                          "serve: Poisson request trace through the continuous-batching server; "
                          "copy: a plain device copy of known size (HBM counter calibration); "
-                         "jacstudy: analytic vs finite-difference Newton Jacobian at S = 10, 30, 53")
+                         "jacstudy: analytic vs finite-difference Newton Jacobian at S = 10, 30, 53; "
+                         "sweep: error against the tight-tolerance truth and cost over rtol x dt")
     ap.add_argument("--lu-fp32", action="store_true", help="FP32 Newton-matrix LU with FP64 refinement")
     ap.add_argument("--jac-reuse", action="store_true",
                     help="keep the factored Newton matrix across attempts while it is recent (CVODE's policy); "
@@ -98,6 +99,8 @@ def main():
         return bench_serve(args, torch, dev, chem, synth)
     if args.mode == "jacstudy":
         return bench_jacstudy(args, torch, dev, chem, synth)
+    if args.mode == "sweep":
+        return bench_sweep(args, torch, dev, chem, synth)
     shape = tuple(int(v) for v in args.shape.split(",")) if args.shape else None
     w = synth.config_workload(args.config, os.path.join(ROOT, "tests", "golden"), shape=shape)
     shape = w.shape if w.shape else shape
@@ -380,6 +383,44 @@ def bench_jacstudy(args, torch, dev, chem, synth):
         row["speedup_kept_matrix_vs_analytic"] = row["analytic"]["kernel_ms"] / row["analytic_kept"]["kernel_ms"]
         rows.append(row)
     print(json.dumps({"mode": "jacstudy", "dtype": "f64", "data": "synthetic", "kernel": "group kernels",
+                      "rows": rows}), flush=True)
+
+
+def bench_sweep(args, torch, dev, chem, synth):
+    """Accuracy against cost over tolerance and substep (the paper's
+    substep-by-tolerance study, Sec. 3.1): flame-box states of G(10,25,3) on the
+    GPU for rtol in {1e-6, 1e-8, 1e-10} and dt in {1e-7, 1e-6, 1e-5} s; the
+    error is measured on a strided sample against the oracle at rtol 1e-12,
+    atol 1e-20."""
+    import oracle
+    golden = os.path.join(ROOT, "tests", "golden")
+    w = synth.config_workload(2, golden, shape=(256, 4, 4))
+    n = w.n_cells
+    sub = np.arange(0, n, n // 48)
+    gm = chem.Mechanism(w.mech.to_text())
+    gm.set_options(q_max=args.q_max, kernel=KERNEL_CODES[args.kernel])
+    om = oracle.Mech(w.mech.to_text())
+    T0 = torch.tensor(w.T, device=dev)
+    Y0 = torch.tensor(w.Y, device=dev)
+    rows = []
+    for dt in (1e-7, 1e-6, 1e-5):
+        print(f"sweep: truth for dt {dt:g} on {sub.size} cells", file=sys.stderr, flush=True)
+        Tt, Yt, _ = om.integrate(w.T[sub], w.Y[:, sub], w.p, dt, 1e-12, 1e-20, nthreads=oracle.max_threads())
+        for rtol in (1e-6, 1e-8, 1e-10):
+            T, Y = T0.clone(), Y0.clone()
+            gm.integrate(T, Y, w.p, dt, rtol, 1e-12)                      # warm-up
+            T.copy_(T0)
+            Y.copy_(Y0)
+            st = gm.integrate(T, Y, w.p, dt, rtol, 1e-12)
+            Tg, Yg = T.cpu().numpy()[sub], Y.cpu().numpy()[:, sub]
+            rows.append({"dt": dt, "rtol": rtol, "kernel_ms": st["wall_ms"], "cells_per_s": n / (st["wall_ms"] * 1e-3),
+                         "steps_per_cell": st["n_steps_total"] / n, "failed_cells": st["n_cells_failed"],
+                         "max_rel_dT_vs_truth": float((np.abs(Tg - Tt) / Tt).max()),
+                         "max_abs_dY_vs_truth": float(np.abs(Yg - Yt).max())})
+            print(f"sweep: dt {dt:g} rtol {rtol:g}: {st['wall_ms']:.1f} ms", file=sys.stderr, flush=True)
+    print(json.dumps({"mode": "sweep", "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": f"flame box 256x4x4 = {n} cells of G(10,25,3,seed 1), atol 1e-12; "
+                                             f"error on {sub.size} strided cells"},
                       "rows": rows}), flush=True)
 
 
