@@ -28,7 +28,7 @@ C_EXP = 20.0                     # FP64 flops charged per exp/log (software sequ
 
 
 def flop_model(S: int, R: int, n_tb: int, n_falloff: int):
-    """Algorithmic FP64 flops per event of the method:
+    """Algorithmic FP64 flops per event of the method (c_exp flops per exp/log):
     per rhs evaluation, per fresh Newton matrix (Jacobian extra work, M = I - cJ
     and its LU; one per attempt unless factors are kept), per attempt (step
     control), per Newton iteration (residual, solve, norm)."""
@@ -83,8 +83,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(cells are independent; see DESIGN.md for how the work would shard).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (cells are independent, so "
+              "each GPU would integrate its own share of the cells).", file=sys.stderr)
         sys.exit(2)
 
     import torch

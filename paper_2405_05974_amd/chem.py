@@ -86,8 +86,7 @@ def load_library(path: Optional[str] = None):
         return _lib
     p = path or LIB_PATH
     if not os.path.exists(p):
-        raise RuntimeError(f"libchem.so not built at {p}; run __graft_entry__.build() "
-                           "(python -m paper_2405_05974_amd.build)")
+        raise RuntimeError(f"libchem.so not built at {p}; build it with python -m paper_2405_05974_amd.build")
     # torch ships its own HIP runtime under the same soname as the system one;
     # loading torch first makes libchem bind to that copy, so the process has
     # one runtime and device pointers/streams from torch are valid here.
