@@ -4,7 +4,8 @@
  * The library advances, in every cell of a batch, the chemical state
  * phi = (Y_1..Y_S, T) of a constant-pressure adiabatic homogeneous reactor
  * over one flow step dt with an implicit BDF integrator whose Newton
- * iteration uses the analytic chemical Jacobian.  This is the per-cell
+ * iteration uses the analytic chemical Jacobian (difference quotients as an
+ * option, CHEM_OPT_JAC).  This is the per-cell
  * problem stated in the paper's Sec. 3.1 (at every time step and in every
  * cell, the production rates of the state are evaluated and the state is
  * advanced implicitly with Newton's method and the Jacobian of Eq. 7); the
@@ -133,10 +134,9 @@ int chem_set_option(chem_mech* m, int key, double value);
  * the state at dt.  rtol > 0, atol >= 0 set the WRMS error weights
  * 1/(rtol |y| + atol) used for every component, T included.  Steps that
  * would leave a mass fraction below -atol are rejected, and one left
- * negative is set to zero (outputs are >= 0);
- * T follows its own equation, so the mixture enthalpy is conserved to the
- * integration tolerance.  stats (host
- * pointer, may be NULL) receives the totals.  Returns CHEM_OK,
+ * negative is set to zero (outputs are >= 0); T follows its own equation,
+ * so the mixture enthalpy is conserved to the integration tolerance.  stats
+ * (host pointer, may be NULL) receives the totals.  Returns CHEM_OK,
  * CHEM_WARN_CELLS_FAILED if any cell failed (see the CHEM_CELL_* codes), or
  * an error code.  n_cells == 0 is a no-op returning CHEM_OK. */
 int chem_integrate(chem_mech* m, int64_t n_cells, double* T, double* Y, double p, double dt,
