@@ -108,7 +108,9 @@ def main():
     n = w.n_cells
     n_tb = sum(r.kind == 1 for r in m.reactions)
     n_fo = sum(r.kind == 2 for r in m.reactions)
+    t_load = time.perf_counter()
     gm = chem.Mechanism(m.to_text())
+    load_ms = (time.perf_counter() - t_load) * 1e3
     gm.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32), kernel=KERNEL_CODES[args.kernel],
                    jac_reuse=int(args.jac_reuse))
     kname = kernel_name(args, m.n_species + 1)
@@ -122,8 +124,12 @@ def main():
         Y.copy_(Y0)
         return gm.integrate(T, Y, w.p, w.dt, w.rtol, w.atol)
 
+    first_ms = None
     for i in range(args.warmup):
+        tw = time.perf_counter()
         st = step()
+        if first_ms is None:
+            first_ms = (time.perf_counter() - tw) * 1e3
         print(f"warmup {i}: {st['wall_ms']:.1f} ms kernel, rc={st['rc']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     kernel_ms, step_ms, stats = [], [], []
@@ -171,6 +177,9 @@ def main():
         },
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
                        "what": "one whole-box chem_integrate call"},
+        "setup_ms": {"mechanism_load": load_ms, "first_call": first_ms,
+                     "what": "parse + table upload; the first call includes compiling the generated kernels "
+                             "(lane-per-cell family) and is not timed in value"},
         "integration": {"steps_per_cell": st["n_steps_total"] / n, "attempts_per_cell": st["n_attempts"] / n,
                         "newton_per_cell": st["n_newton_iters"] / n, "max_steps_cell": st["n_steps_max"],
                         "failed_cells": st["n_cells_failed"]},
