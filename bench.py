@@ -24,29 +24,47 @@ sys.path.insert(0, ROOT)
 
 METRIC = "reactor cells integrated/sec over dt (1 GPU) at stated accuracy; p50/p99 box latency"
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/clk)
-C_EXP = 20.0                     # FP64 flops charged per exp/log (software sequence on gfx950)
+C_EXP_DEFAULT = 20.0             # FP64 operations per exp when no measured figure is on file
 
 
-def flop_model(S: int, R: int, n_tb: int, n_falloff: int):
-    """Algorithmic FP64 flops per event of the method (c_exp flops per exp/log):
-    per rhs evaluation, per fresh Newton matrix (Jacobian extra work, M = I - cJ
-    and its LU; one per attempt unless factors are kept), per attempt (step
-    control), per Newton iteration (residual, solve, norm)."""
+def probe_figures():
+    """Measured probe figures committed under profiles/ (on-box FP64 FMA rate
+    and the FP64 operations of one exp per kernel family), or {}."""
+    path = os.path.join(ROOT, "profiles", "probe_fp64_exp.json")
+    return json.load(open(path)) if os.path.exists(path) else {}
+
+
+def flops_survey_model(stats, S, R, c_exp, q):
+    """Algorithmic FP64 flops of one launch by the per-step model
+
+        F_step = n_N F_rhs + F_J + 2N^3/3 + n_N 2N^2 + 10 N q,
+        F_rhs = R (2 c_exp + 14) + 12 S + 8 R,   F_J = 64 R + 2 S^2 + 6 N^2,
+
+    summed with the launch's own counters: every right-hand side (n_rhs, the
+    Newton iterations plus one per cell to start), every fresh Newton matrix
+    (n_jac Jacobians and factorisations), every Newton solve and every step
+    attempt (order q taken as q_max, an upper bound of a term worth ~2%)."""
     N = S + 1
-    nnz = 4 * R                                   # nonzeros of nu (<= 2 + 2 per reaction)
-    f_rhs = 32 * S + S * C_EXP + R * (26 + 2 * C_EXP) + n_falloff * (8 + C_EXP) + n_tb + 2 * nnz
-    f_jac = 26 * R + 12 * nnz + 13 * S * S + 10 * N
+    f_rhs = R * (2 * c_exp + 14) + 12 * S + 8 * R
+    f_j = 64 * R + 2 * S * S + 6 * N * N
     f_lu = 2.0 * N ** 3 / 3.0
-    f_setup = f_jac + 2 * N * N + f_lu
-    f_control = 40 * N
-    f_newton = 2 * N * N + 7 * N
-    return f_rhs, f_setup, f_control, f_newton
+    return (stats["n_rhs"] * f_rhs + stats["n_jac"] * (f_j + f_lu) + stats["n_newton_iters"] * 2 * N * N
+            + stats["n_attempts"] * 10 * N * q)
 
 
-def algorithmic_flops(stats, S, R, n_tb, n_falloff):
-    f_rhs, f_setup, f_control, f_newton = flop_model(S, R, n_tb, n_falloff)
-    return (stats["n_rhs"] * f_rhs + stats["n_jac"] * f_setup + stats["n_attempts"] * f_control
-            + stats["n_newton_iters"] * f_newton)
+def flops_itemised_model(stats, S, R, n_tb, n_falloff, c_exp=20.0):
+    """A finer itemisation of the same work (per rhs: mixture, thermo with one
+    exp/log per species, rates with two exps per reaction, falloff, sparse
+    products; per fresh matrix: Jacobian extras, M = I - cJ and its LU; per
+    attempt: step control; per Newton iteration: residual, solve, norm).  It
+    charges more per rhs than the model above and is reported beside it."""
+    N = S + 1
+    nnz = 4 * R
+    f_rhs = 32 * S + S * c_exp + R * (26 + 2 * c_exp) + n_falloff * (8 + c_exp) + n_tb + 2 * nnz
+    f_jac = 26 * R + 12 * nnz + 13 * S * S + 10 * N
+    f_setup = f_jac + 2 * N * N + 2.0 * N ** 3 / 3.0
+    return (stats["n_rhs"] * f_rhs + stats["n_jac"] * f_setup + stats["n_attempts"] * 40 * N
+            + stats["n_newton_iters"] * (2 * N * N + 7 * N))
 
 
 def main():
@@ -59,15 +77,17 @@ def main():
     ap.add_argument("--config", type=int, choices=[2, 3], default=2,
                     help="flame workload: 2 = G(10,25,3,s1), dt 2e-6, rtol 1e-8 (the headline box); "
                          "3 = G(53,325,4,s2), dt 1e-6, rtol 1e-6 (the mixed-precision case, with --lu-fp32)")
-    ap.add_argument("--cpu-sample", type=int, default=16384, help="cells in the CPU-oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=8192, help="cells in the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--q-max", type=int, default=5)
-    ap.add_argument("--mode", choices=["flame", "boxes", "serve", "copy", "jacstudy", "sweep"], default="flame",
+    ap.add_argument("--mode", choices=["flame", "boxes", "serve", "copy", "jacstudy", "sweep", "peak"],
+                    default="flame",
                     help="flame: the headline box; boxes: uneven AMR boxes in one persistent launch; "
                          "serve: Poisson request trace through the continuous-batching server; "
                          "copy: a plain device copy of known size (HBM counter calibration); "
                          "jacstudy: analytic vs finite-difference Newton Jacobian at S = 10, 30, 53; "
-                         "sweep: error against the tight-tolerance truth and cost over rtol x dt")
+                         "sweep: error against the tight-tolerance truth and cost over rtol x dt; "
+                         "peak: the FP64 FMA rate and the cost of one exp on this device (probe kernels)")
     ap.add_argument("--lu-fp32", action="store_true", help="FP32 Newton-matrix LU with FP64 refinement")
     ap.add_argument("--jac-reuse", action="store_true",
                     help="keep the factored Newton matrix across attempts while it is recent (CVODE's policy); "
@@ -93,6 +113,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.mode == "copy":
         return copy_calibration(torch, dev)
+    if args.mode == "peak":
+        return probe_peak(torch)
     if args.mode == "boxes":
         return bench_boxes(args, torch, dev, chem, synth)
     if args.mode == "serve":
@@ -148,11 +170,19 @@ def main():
         print(f"warning: {st['n_cells_failed']} cells failed", file=sys.stderr)
     ms_per_step = elapsed * 1e3 / args.steps
     value = n * args.steps / elapsed
-    flops = algorithmic_flops(st, m.n_species, m.n_reactions, n_tb, n_fo)
     k_ms = float(np.median(kernel_ms))
-    achieved = flops / (k_ms * 1e-3) / 1e12
     lane = kname.startswith("chem_lpc_integrate")
+    probes = probe_figures()
+    c_exp = probes.get("c_exp_chexp" if lane else "c_exp_libexp", C_EXP_DEFAULT)
+    flops = flops_survey_model(st, m.n_species, m.n_reactions, c_exp, args.q_max)
+    flops_item = flops_itemised_model(st, m.n_species, m.n_reactions, n_tb, n_fo)
+    achieved = flops / (k_ms * 1e-3) / 1e12
     prof = measured_profile("chem_lpc_integrate") if (lane and args.config == 2 and shape == (256, 64, 64)) else None
+    hw_frac = None
+    if prof and "fp64_flops_per_launch_hw" in prof:
+        # executed FP64 flops counted on all 64 lanes, weighted by the measured lane activity
+        hw = prof["fp64_flops_per_launch_hw"] * prof.get("lane_activity", 1.0)
+        hw_frac = hw / (k_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS
     out = {
         "metric": METRIC,
         "value": value,
@@ -188,15 +218,46 @@ def main():
             "frac": achieved / FP64_PEAK_TFLOPS,
             "traffic": prof["hbm_bytes_per_launch"] if prof else None,
             "kernel": kname, "kernel_ms": k_ms, "flops_per_launch": flops,
-            "hw_counter_frac": (prof["fp64_flops_per_launch_hw"] / (k_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS
-                                if prof and "fp64_flops_per_launch_hw" in prof else None),
+            "flop_model": (f"per step n_N F_rhs + F_J + 2N^3/3 + n_N 2N^2 + 10Nq with F_rhs = R(2c_exp+14)+12S+8R, "
+                           f"F_J = 64R+2S^2+6N^2, c_exp = {c_exp:g} (measured FP64 operations of one exp of this "
+                           f"kernel family), q = {args.q_max}; summed over the launch's rhs, Jacobian, Newton and "
+                           f"attempt counts"),
+            "itemised_model": {"flops_per_launch": flops_item,
+                               "frac": flops_item / (k_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                               "what": "finer per-event itemisation (bench.py flops_itemised_model, c_exp 20)"},
+            "hw_counter_frac": hw_frac,
+            "hw_counter_what": "SQ_INSTS_VALU_FLOPS_FP64 x 64 x lane activity (SQ_THREAD_CYCLES_VALU / "
+                               "(64 SQ_ACTIVE_INST_VALU)) from the committed profile of this kernel's sources",
+            "peak_measured": probes.get("fma_tflops"),
+            "peak_measured_what": "FP64 FMA chains on every CU (bench.py --mode peak), beside the published peak",
             "mfma_utilisation": 0.0,
             "timing": "kernel_ms = median of the timed launches (HIP events on the launch stream)",
         },
     }
+    if args.lu_fp32:
+        out["accuracy_vs_fp64_gpu"] = fp64_comparison(gm, T0, Y0, T, Y, w, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["accuracy"] = cpu_baseline(w, T, Y, args)
     print(json.dumps(out), flush=True)
+
+
+def fp64_comparison(gm, T0, Y0, T, Y, w, torch):
+    """Every cell of the FP32-LU result (T, Y) against the plain FP64 GPU path
+    on the same inputs (T0, Y0) and settings: the difference isolates the LU
+    precision.  Errors are absolute in Y and relative in T, max and p99 over
+    the cells."""
+    print("fp64 comparison: plain FP64 integration of the same box", file=sys.stderr, flush=True)
+    gm.set_options(lu_fp32=0)
+    T6, Y6 = T0.clone(), Y0.clone()
+    st = gm.integrate(T6, Y6, w.p, w.dt, w.rtol, w.atol)
+    gm.set_options(lu_fp32=1)
+    print(f"fp64 comparison: {st['wall_ms']:.1f} ms", file=sys.stderr, flush=True)
+    dY = (Y - Y6).abs().amax(dim=0)
+    dT = ((T - T6).abs() / T6)
+    q = lambda t: float(torch.quantile(t.float().cpu(), 0.99))
+    return {"vs": "plain FP64 GPU path, same inputs and settings, every cell", "cells": int(T.numel()),
+            "max_abs_dY": float(dY.max()), "p99_abs_dY": q(dY), "max_rel_dT": float(dT.max()), "p99_rel_dT": q(dT),
+            "fp64_kernel_ms": st["wall_ms"]}
 
 
 def measured_profile(kernel):
@@ -229,19 +290,32 @@ def kernel_name(args, N):
 
 
 def cpu_baseline(w, Tg, Yg, args):
-    """The oracle on a strided sample of the same box, all host threads."""
+    """The oracle, built for this host (-march=native), on a strided sample of
+    the same box with all host threads: the median of three timed runs; the
+    results also give the accuracy figures."""
+    import tempfile
     import oracle
     n = w.n_cells
     k = max(1, min(args.cpu_sample, n))
     idx = np.unique(np.linspace(0, n - 1, k).astype(np.int64))
-    om = oracle.Mech(w.mech.to_text())
+    tmpdir = tempfile.mkdtemp(prefix="oracle_native_")
+    try:
+        lib_path = oracle.build_native(tmpdir)
+        build = "gcc -O3 -march=native -fopenmp -ffp-contract=off (no fast-math)"
+    except Exception as exc:             # keep the portable build if the host compiler refuses
+        print(f"cpu baseline: native build failed ({exc}); using the portable build", file=sys.stderr, flush=True)
+        lib_path, build = None, "gcc -O3 -fopenmp -ffp-contract=off (portable build)"
+    om = oracle.Mech(w.mech.to_text(), lib_path=lib_path)
     threads = oracle.max_threads()
-    print(f"cpu baseline: oracle on {idx.size} cells, {threads} threads", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    To, Yo, so = om.integrate(w.T[idx], w.Y[:, idx], w.p, w.dt, w.rtol, w.atol, q_max=args.q_max,
-                              nthreads=threads, jac_reuse=args.jac_reuse)
-    el = time.perf_counter() - t0
-    print(f"cpu baseline: {el:.1f} s", file=sys.stderr, flush=True)
+    runs = []
+    for r in range(3):
+        print(f"cpu baseline: oracle run {r + 1}/3 on {idx.size} cells, {threads} threads", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        To, Yo, so = om.integrate(w.T[idx], w.Y[:, idx], w.p, w.dt, w.rtol, w.atol, q_max=args.q_max,
+                                  nthreads=threads, jac_reuse=args.jac_reuse, want_stats=(r == 0))
+        runs.append(time.perf_counter() - t0)
+        print(f"cpu baseline: {runs[-1]:.1f} s", file=sys.stderr, flush=True)
+    el = float(np.median(runs))
     Tgs = Tg.cpu().numpy()[idx]
     Ygs = Yg.cpu().numpy()[:, idx]
     acc = {"vs": "CPU oracle, same inputs and settings", "cells": int(idx.size),
@@ -250,10 +324,10 @@ def cpu_baseline(w, Tg, Yg, args):
            "p99_abs_dY": float(np.percentile(np.abs(Ygs - Yo).max(axis=0), 99)),
            "p99_rel_dT": float(np.percentile(np.abs(Tgs - To) / To, 99))}
     # against the tight-tolerance truth (the oracle at rtol 1e-12, atol 1e-20, fresh Newton matrices)
-    # on a sub-sample of at most 256 cells sized to about 45 s of host time; a truth cell costs about
+    # on a sub-sample of at most 128 cells sized to about 20 s of host time; a truth cell costs about
     # 8x a same-settings cell, 20x when the same-settings run kept its Newton matrices
     per_cell_truth = el * threads / idx.size * (20.0 if args.jac_reuse else 8.0)
-    n_sub = int(min(256, idx.size, 45.0 * threads / per_cell_truth))
+    n_sub = int(min(128, idx.size, 20.0 * threads / per_cell_truth))
     if n_sub < 4:
         acc["vs_truth"] = {"cells": 0, "what": f"skipped: about {per_cell_truth:.0f} s per truth cell on one core"}
     else:
@@ -261,14 +335,16 @@ def cpu_baseline(w, Tg, Yg, args):
         pos = np.searchsorted(idx, sub)
         print(f"cpu baseline: truth reference on {sub.size} cells", file=sys.stderr, flush=True)
         Tt, Yt, _ = om.integrate(w.T[sub], w.Y[:, sub], w.p, w.dt, 1e-12, 1e-20, q_max=args.q_max,
-                                 nthreads=threads)
+                                 nthreads=threads, want_stats=False)
         acc["vs_truth"] = {"cells": int(sub.size), "max_abs_dY_gpu": float(np.abs(Ygs[:, pos] - Yt).max()),
                            "max_rel_dT_gpu": float((np.abs(Tgs[pos] - Tt) / Tt).max()),
                            "max_abs_dY_oracle": float(np.abs(Yo[:, pos] - Yt).max()),
+                           "max_rel_dT_oracle": float((np.abs(To[pos] - Tt) / Tt).max()),
                            "what": "truth = the oracle at rtol 1e-12, atol 1e-20"}
-    # one core on a sub-sample of about 5 s
-    n1 = int(max(1, min(idx.size, 5.0 * idx.size / (el * threads))))
+    # one core on a sub-sample of about 4 s
+    n1 = int(max(1, min(idx.size, 4.0 * idx.size / (el * threads))))
     sub1 = idx[:: max(1, idx.size // n1)]
+    print(f"cpu baseline: one core on {sub1.size} cells", file=sys.stderr, flush=True)
     t1 = time.perf_counter()
     om.integrate(w.T[sub1], w.Y[:, sub1], w.p, w.dt, w.rtol, w.atol, q_max=args.q_max, nthreads=1,
                  jac_reuse=args.jac_reuse, want_stats=False)
@@ -283,7 +359,9 @@ def cpu_baseline(w, Tg, Yg, args):
     except OSError:
         pass
     base = {"value": idx.size / el, "unit": "cells/s", "cores": threads, "kind": "oracle",
-            "sample": f"{idx.size} cells evenly strided over the {n}-cell box ({el:.1f} s)",
+            "sample": (f"{idx.size} cells evenly strided over the {n}-cell box; median of 3 runs "
+                       f"({', '.join(f'{r:.1f}' for r in runs)} s)"),
+            "build": build,
             "one_core": {"value": sub1.size / el1, "cells": int(sub1.size), "seconds": el1},
             "cpu_model": model}
     return base, acc
@@ -300,6 +378,36 @@ def copy_calibration(torch, dev):
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"mode": "copy", "bytes_read_per_dispatch": n * 8, "bytes_written_per_dispatch": n * 8}))
+
+
+def probe_peak(torch):
+    """The probe kernels of libchem_probe.so: FP64 FMA throughput over the
+    whole chip, and timed exp loops (their FP64 instruction counters, taken
+    with rocprofv3 --pmc on this mode, give the operations of one exp)."""
+    import ctypes as C
+    torch.cuda.init()
+    lib = C.CDLL(os.path.join(ROOT, "paper_2405_05974_amd", "libchem_probe.so"))
+    lib.chem_probe_run.argtypes = [C.c_char_p, C.c_int, C.c_int, C.POINTER(C.c_double)]
+    ms = C.c_double()
+    out = {"mode": "peak"}
+    blocks, iters = 8192, 2048
+    for i in range(3):
+        if lib.chem_probe_run(b"fma", blocks, iters, C.byref(ms)) != 0:
+            raise RuntimeError("fma probe failed")
+        flops = 2.0 * 16 * iters * blocks * 256
+        out.setdefault("fma_tflops_runs", []).append(flops / (ms.value * 1e-3) / 1e12)
+        print(f"peak: fma run {i}: {out['fma_tflops_runs'][-1]:.2f} TFLOP/s", file=sys.stderr, flush=True)
+    out["fma_tflops"] = max(out["fma_tflops_runs"])
+    eb, ei = 2048, 4096
+    for which in ("loop", "chexp", "libexp"):
+        if lib.chem_probe_run(which.encode(), eb, ei, C.byref(ms)) != 0:
+            raise RuntimeError(f"{which} probe failed")
+        out[f"{which}_ns_per_eval_per_lane"] = ms.value * 1e6 / (eb * 256 * ei) * 256 * 1024
+        out[f"{which}_dispatch"] = {"blocks": eb, "threads": 256, "iters": ei, "ms": ms.value}
+        print(f"peak: {which}: {ms.value:.2f} ms", file=sys.stderr, flush=True)
+    out["what"] = ("fma: 16 independent FMA chains per thread, 8192 blocks of 256 threads, 2048 trips; "
+                   "exp probes: 2048 blocks of 256 threads, 4096 exps per thread, arguments in [-60, -19]")
+    print(json.dumps(out), flush=True)
 
 
 def bench_boxes(args, torch, dev, chem, synth):

@@ -229,9 +229,12 @@ void chem_server_destroy(chem_server* s);
 
 /* Rates of one state per cell (Eq. 2-3, Eq. 7): wdot[S * n] (mol m^-3 s^-1,
  * required), f[(S+1) * n] (optional, the ODE right-hand side dY/dt, dT/dt)
- * and jac[(S+1)^2 * n] (optional, J[i][j] = d f_i / d y_j stored at
- * (i*(S+1)+j) * n + cell).  T, Y as in chem_integrate; p in Pa.  The
- * CHEM_OPT_FIXED_T option applies to f and jac. */
+ * and jac[(S+1)^2 * n] (optional, the analytic J[i][j] = d f_i / d y_j stored
+ * at (i*(S+1)+j) * n + cell).  T, Y as in chem_integrate; p in Pa.  The
+ * CHEM_OPT_FIXED_T option applies to f and jac.  The values come from the
+ * kernel family chem_integrate would run with the handle's options
+ * (CHEM_OPT_KERNEL), so each family's rate and Jacobian code can be checked
+ * on its own. */
 int chem_rates(chem_mech* m, int64_t n_cells, const double* T, const double* Y, double p, double* wdot,
                double* f, double* jac);
 

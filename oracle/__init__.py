@@ -23,11 +23,19 @@ BUILD_CMD = ["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-con
              "-fno-fast-math", "-Wall", "-Wno-unused-result", _SRC, "-o", _LIB, "-lm"]
 
 
-def build(extra_flags=()) -> str:
-    """Compile oracle.c into liboracle.so (always recompiles)."""
+def build(extra_flags=(), out: Optional[str] = None) -> str:
+    """Compile oracle.c into liboracle.so, or into `out` (always recompiles)."""
     cmd = BUILD_CMD[:1] + list(extra_flags) + BUILD_CMD[1:]
+    if out is not None:
+        cmd[cmd.index(_LIB)] = out
     subprocess.run(cmd, check=True)
-    return _LIB
+    return out or _LIB
+
+
+def build_native(out_dir: str) -> str:
+    """The same oracle built for the host it runs on (-march=native) into
+    out_dir, for timing: rounding is unchanged (no contraction, no fast-math)."""
+    return build(["-march=native"], out=os.path.join(out_dir, "liboracle_native.so"))
 
 
 class OrcOpts(C.Structure):

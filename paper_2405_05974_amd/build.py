@@ -8,6 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libchem.so")
+PROBE_LIB = os.path.join(HERE, "libchem_probe.so")
 ARCH = os.environ.get("CHEM_OFFLOAD_ARCH", "gfx950")
 
 HIP_FLAGS = [
@@ -21,7 +22,8 @@ SOURCES = [os.path.join(CSRC, "chem_kernels.hip"), os.path.join(CSRC, "chem_host
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every source into paper_2405_05974_amd/libchem.so (always rebuilds)."""
+    """Compile every source into paper_2405_05974_amd/libchem.so, and the measurement
+    probes into libchem_probe.so (always rebuilds)."""
     objs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.basename(src) + ".o")
@@ -39,6 +41,14 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    # measurement probes (FP64 FMA rate, cost of one exp), a library of their own
+    probe_src = os.path.join(CSRC, "chem_probe.cpp")
+    tmp = PROBE_LIB + ".tmp"
+    cmd = ["hipcc", *HIP_FLAGS, "-x", "hip", "-shared", probe_src, "-o", tmp, "-lhiprtc"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, PROBE_LIB)
     return LIB
 
 

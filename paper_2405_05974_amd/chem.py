@@ -278,8 +278,8 @@ class Server:
         """None while pending, else (T, Y, latency_ms, status)."""
         import numpy as np
         S, n = self._meta[rid]
-        T = np.empty(n)
-        Y = np.empty((S, n))
+        T = np.full(n, np.nan)              # left as NaN when the request failed
+        Y = np.full((S, n), np.nan)
         lat = C.c_double()
         status = C.c_int()
         rc = _check(self.lib, self.lib.chem_server_poll(self.h, rid, T.ctypes.data if n else None,

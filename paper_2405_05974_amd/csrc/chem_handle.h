@@ -50,6 +50,7 @@ struct chem_mech {
   std::string lpc_src;
   void* lpc_integrate = nullptr;
   void* lpc_boxes = nullptr;
+  void* lpc_rates = nullptr;
   int lpc_device = -1;
   int lpc_reuse = -1;   // CH_REUSE of the loaded module
   // workspace
@@ -67,14 +68,15 @@ struct chem_mech {
   int* host_done_dev = nullptr;
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t graph = nullptr;
-  const void* graph_key[4] = {nullptr, nullptr, nullptr, nullptr};
+  const void* graph_key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   int graph_grid = 0, graph_np = 0, graph_f32 = -1;
   chemgpu::IntParams graph_prm{};   // integration parameters baked into the captured launch
 };
 
 namespace chemgpu {
 std::string lpc_source(const HostMech& m, bool reuse);
-int lpc_module(const std::string& src, int device, void** integrate_fn, void** boxes_fn, std::string& log);
+int lpc_module(const std::string& src, int device, void** integrate_fn, void** boxes_fn, void** rates_fn,
+               std::string& log);
 }  // namespace chemgpu
 
 // Kernel family for the next integration with this handle's options: sets

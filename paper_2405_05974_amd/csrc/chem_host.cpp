@@ -334,7 +334,7 @@ int chem_select_kernel(chem_mech* m, bool* lpc) {
   if (m->lpc_integrate && m->lpc_device == m->device && m->lpc_reuse == reuse) return CHEM_OK;
   if (m->lpc_src.empty() || m->lpc_reuse != reuse) m->lpc_src = chemgpu::lpc_source(m->host, reuse != 0);
   std::string log;
-  if (chemgpu::lpc_module(m->lpc_src, m->device, &m->lpc_integrate, &m->lpc_boxes, log) != 0)
+  if (chemgpu::lpc_module(m->lpc_src, m->device, &m->lpc_integrate, &m->lpc_boxes, &m->lpc_rates, log) != 0)
     return fail(CHEM_ERR_DEVICE, log);
   m->lpc_device = m->device;
   m->lpc_reuse = reuse;
@@ -668,6 +668,9 @@ int ensure_boxes(chem_mech* m, int n_boxes) {
   if (!m->capture_stream && hipStreamCreateWithFlags(&m->capture_stream, hipStreamNonBlocking) != hipSuccess)
     return fail(CHEM_ERR_DEVICE, "hipStreamCreate");
   if (n_boxes <= m->box_cap) return CHEM_OK;
+  // a captured graph holds the old buffers' addresses
+  if (m->graph) (void)hipGraphExecDestroy(m->graph);
+  m->graph = nullptr;
   if (m->dboxes) (void)hipFree(m->dboxes);
   if (m->dremaining) (void)hipFree(m->dremaining);
   if (m->host_done) (void)hipHostFree(m->host_done);
@@ -770,7 +773,7 @@ int chem_integrate_boxes(chem_mech* m, int n_boxes, const chem_box* boxes, doubl
     e = hipEventRecord(m->ev0, m->stream);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     if (m->use_graph) {
-      const void* key[4] = {m->rec, m->dboxes, m->host_done_dev, m->blob};
+      const void* key[6] = {m->rec, m->dboxes, m->host_done_dev, m->blob, m->dremaining, m->dhead};
       const bool stale = !m->graph || std::memcmp(key, m->graph_key, sizeof key) != 0 || m->graph_grid != grid ||
                          m->graph_np != (lpc ? 1 : m->dev.np_width) || m->graph_f32 != m->lu_fp32 ||
                          old_rec != m->rec ||
@@ -946,7 +949,12 @@ int chem_rates(chem_mech* m, int64_t n_cells, const double* T, const double* Y, 
   if (!(p > 0) || !std::isfinite(p)) return fail(CHEM_ERR_ARG, "p must be positive");
   if (n_cells == 0) return CHEM_OK;
   if (!T || !Y || !wdot) return fail(CHEM_ERR_ARG, "T, Y or wdot is NULL");
-  hipError_t e = chemgpu::launch_rates(m->dev, p, m->fixed_T, T, Y, n_cells, wdot, f, jac, m->stream);
+  // the same kernel family chem_integrate would use for these options
+  bool lpc = false;
+  const int krc = chem_select_kernel(m, &lpc);
+  if (krc != CHEM_OK) return krc;
+  hipError_t e = lpc ? chemgpu::launch_lpc_rates(m->lpc_rates, p, m->fixed_T, T, Y, n_cells, wdot, f, jac, m->stream)
+                     : chemgpu::launch_rates(m->dev, p, m->fixed_T, T, Y, n_cells, wdot, f, jac, m->stream);
   if (e != hipSuccess) return hip_fail(e, "rates kernel launch");
   e = hipStreamSynchronize(m->stream);
   if (e != hipSuccess) return hip_fail(e, "rates");

@@ -93,6 +93,8 @@ hipError_t launch_boxes_init(const BoxDev* boxes, const BoxJob* job, unsigned* h
 constexpr int kLpcMaxN = 12;
 hipError_t launch_lpc_integrate(void* fn, const IntParams& prm, double* T, double* Y, int64_t n, int32_t* rec,
                                 hipStream_t stream);
+hipError_t launch_lpc_rates(void* fn, double p, int fixed_T, const double* T, const double* Y, int64_t n,
+                            double* wdot, double* f, double* jac, hipStream_t stream);
 hipError_t launch_lpc_boxes(void* fn, const IntParams& prm, const BoxDev* boxes, const BoxJob* job, unsigned* head,
                             int* remaining, int32_t* rec, int* host_done, int grid, hipStream_t stream);
 

@@ -35,6 +35,10 @@ const char* kLpcBody =
 #include "chem_lpc_body.inc"
     ;
 
+const char* kChExp =
+#include "chem_exp.inc"
+    ;
+
 // exact double literal (hexadecimal floating point)
 std::string lit(double v) {
   if (v == 0.0) return std::signbit(v) ? "(-0.0)" : "0.0";
@@ -93,8 +97,9 @@ std::string lpc_source(const HostMech& m, bool reuse) {
       for (int k : x.prod) needG[k] = 1;
     }
   const double kcal_to_K = 4184.0 / kRu;
-  o << "template <bool JAC>\n__device__ __forceinline__ void ch_eval(const double (&y)[CH_N], const double p, "
-       "const int fixedT, double (&f)[CH_N], double (&J)[CH_N][CH_N]) {\n";
+  // WD: also hand back the net production rates (mol cm^-3 s^-1) for chem_rates
+  o << "template <bool JAC, bool WD = false>\n__device__ __forceinline__ void ch_eval(const double (&y)[CH_N], "
+       "const double p, const int fixedT, double (&f)[CH_N], double (&J)[CH_N][CH_N], double* wdo = nullptr) {\n";
   // K reads the table through the constant address space, so loads stay scalar.  At the top
   // and before each reaction the pointer passes through an empty asm statement: the compiler
   // can no longer hoist every table load out of the step loop (about 130 doubles kept live in
@@ -224,6 +229,7 @@ std::string lpc_source(const HostMech& m, bool reuse) {
   o << "  const double iden = 1.0 / den;\n";
   for (int k = 0; k < S; ++k) o << "  f[" << k << "] = " << kc(m.W[k]) << " * wd[" << k << "] * irho;\n";
   o << "  f[CH_S] = fixedT ? 0.0 : -num * iden;\n";
+  o << "  if (WD) {\n#pragma unroll\n    for (int k = 0; k < CH_S; ++k) wdo[k] = wd[k];\n  }\n";
   // Jacobian: row sums AC_k = sum_c A_kc C_c and the temperature row (which
   // needs the column sums sum_k H_k A_kc) from A, then the species rows in place
   o << "  if (JAC) {\n";
@@ -266,31 +272,8 @@ std::string lpc_source(const HostMech& m, bool reuse) {
   for (size_t i = 0; i < pool.size(); ++i) head << (i ? ", " : "") << lit(pool[i]);
   if (pool.empty()) head << "0.0";
   head << "};\n";
-  // exp for the rate constants: reduction x = n ln2 + r with ln 2 split in two
-  // parts, the degree-13 Taylor polynomial of e^r on |r| <= ln2/2, and a
-  // scaling by 2^n.  Within 1 ulp of the C library's exp on [-745, 709]; no
-  // special-case branches, so it serves the finite, moderate arguments of the
-  // rate expressions (a non-finite state fails its Newton iteration either way).
-  head << "__device__ __forceinline__ double ch_exp(const double x) {\n"
-          "  const double n = __builtin_rint(x * 0x1.71547652b82fep+0);\n"
-          "  double r = __builtin_fma(-n, 0x1.62e42fefa39efp-1, x);\n"
-          "  r = __builtin_fma(-n, 0x1.abc9e3b39803fp-56, r);\n"
-          "  double p = 1.0 / 6227020800.0;\n"
-          "  p = __builtin_fma(p, r, 1.0 / 479001600.0);\n"
-          "  p = __builtin_fma(p, r, 1.0 / 39916800.0);\n"
-          "  p = __builtin_fma(p, r, 1.0 / 3628800.0);\n"
-          "  p = __builtin_fma(p, r, 1.0 / 362880.0);\n"
-          "  p = __builtin_fma(p, r, 1.0 / 40320.0);\n"
-          "  p = __builtin_fma(p, r, 1.0 / 5040.0);\n"
-          "  p = __builtin_fma(p, r, 1.0 / 720.0);\n"
-          "  p = __builtin_fma(p, r, 1.0 / 120.0);\n"
-          "  p = __builtin_fma(p, r, 1.0 / 24.0);\n"
-          "  p = __builtin_fma(p, r, 1.0 / 6.0);\n"
-          "  p = __builtin_fma(p, r, 0.5);\n"
-          "  p = __builtin_fma(p, r, 1.0);\n"
-          "  p = __builtin_fma(p, r, 1.0);\n"
-          "  return __builtin_ldexp(p, (int)n);\n"
-          "}\n";
+  // exp for the rate constants (chem_exp.inc)
+  head << kChExp;
   return head.str() + o.str() + kLpcBody;
 }
 
@@ -300,6 +283,7 @@ struct LpcModule {
   hipModule_t mod = nullptr;
   hipFunction_t integrate = nullptr;
   hipFunction_t boxes = nullptr;
+  hipFunction_t rates = nullptr;
 };
 
 std::mutex g_jit_mu;
@@ -308,13 +292,15 @@ std::map<std::pair<int, std::string>, LpcModule> g_jit_cache;   // (device, sour
 }  // namespace
 
 // Compile (or fetch) the lane-per-cell module of `src` for the current device.
-int lpc_module(const std::string& src, int device, void** integrate_fn, void** boxes_fn, std::string& log) {
+int lpc_module(const std::string& src, int device, void** integrate_fn, void** boxes_fn, void** rates_fn,
+               std::string& log) {
   std::lock_guard<std::mutex> lk(g_jit_mu);
   auto key = std::make_pair(device, src);
   auto it = g_jit_cache.find(key);
   if (it != g_jit_cache.end()) {
     *integrate_fn = it->second.integrate;
     *boxes_fn = it->second.boxes;
+    *rates_fn = it->second.rates;
     return 0;
   }
   hipDeviceProp_t prop;
@@ -352,13 +338,15 @@ int lpc_module(const std::string& src, int device, void** integrate_fn, void** b
   LpcModule mod;
   if (hipModuleLoadData(&mod.mod, code.data()) != hipSuccess ||
       hipModuleGetFunction(&mod.integrate, mod.mod, "chem_lpc_integrate") != hipSuccess ||
-      hipModuleGetFunction(&mod.boxes, mod.mod, "chem_lpc_boxes") != hipSuccess) {
+      hipModuleGetFunction(&mod.boxes, mod.mod, "chem_lpc_boxes") != hipSuccess ||
+      hipModuleGetFunction(&mod.rates, mod.mod, "chem_lpc_rates") != hipSuccess) {
     log = "loading the lane-per-cell module failed";
     return -1;
   }
   g_jit_cache[key] = mod;
   *integrate_fn = mod.integrate;
   *boxes_fn = mod.boxes;
+  *rates_fn = mod.rates;
   return 0;
 }
 
@@ -390,6 +378,15 @@ hipError_t launch_lpc_integrate(void* fn, const IntParams& prm, double* T, doubl
   LpcParams q = lpc_params(prm);
   long long nn = n;
   void* args[] = {&T, &Y, &nn, &rec, &q};
+  const unsigned blocks = (unsigned)((n + 63) / 64);
+  return hipModuleLaunchKernel((hipFunction_t)fn, blocks, 1, 1, 64, 1, 1, 0, stream, args, nullptr);
+}
+
+hipError_t launch_lpc_rates(void* fn, double p, int fixed_T, const double* T, const double* Y, int64_t n,
+                            double* wdot, double* f, double* jac, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  long long nn = n;
+  void* args[] = {&T, &Y, &nn, &p, &fixed_T, &wdot, &f, &jac};
   const unsigned blocks = (unsigned)((n + 63) / 64);
   return hipModuleLaunchKernel((hipFunction_t)fn, blocks, 1, 1, 64, 1, 1, 0, stream, args, nullptr);
 }

@@ -304,6 +304,9 @@ void dispatcher(chem_server* s) {
       s->ready.swap(rest);
       if (!launch_group(s, *free_slot, group)) {
         s->err = "launch failed";
+        // copies already queued on the slot's stream may still read or write
+        // the requests' arena regions: let them finish before releasing
+        (void)hipStreamSynchronize(free_slot->stream);
         for (Request* r : group) {   // report the failure on the requests
           r->status = CHEM_ERR_DEVICE;
           r->state = 3;
@@ -410,8 +413,12 @@ int chem_server_poll(chem_server* s, int64_t id, double* T_out, double* Y_out, d
   Request* r = it->second;
   if (r->state != 3) return 0;
   const size_t n = (size_t)r->n;
-  if (T_out && n) std::memcpy(T_out, r->out.data(), sizeof(double) * n);
-  if (Y_out && n) std::memcpy(Y_out, r->out.data() + n, sizeof(double) * (r->out.size() - n));
+  // a request that failed before its results came back has no outputs: the
+  // caller's arrays are left alone and the status says why
+  if (n && r->out.size() == (size_t)(r->m->dev.S + 1) * n) {
+    if (T_out) std::memcpy(T_out, r->out.data(), sizeof(double) * n);
+    if (Y_out) std::memcpy(Y_out, r->out.data() + n, sizeof(double) * (r->out.size() - n));
+  }
   if (latency_ms) *latency_ms = r->latency_ms;
   if (status) *status = r->status;
   s->reqs.erase(it);
