@@ -350,7 +350,11 @@ def test_integration_at_pressure(chem, torch_dev, p, kernel):
     assert st["rc"] == 0 and (rec[0] == 0).all()
     assert_parity(Tg, Yg, To, Yo, f"G(10,25,3,s5) at {p:g} Pa")
     To1, Yo1, _ = oracle_integrate(text, w.T, w.Y, synth.P_ATM, w.dt, w.rtol, w.atol)
-    assert np.abs(Yo1 - Yo).max() > 1e-6        # the pressure changes the answer
+    # the pressure changes the answer by several times the parity bar (the mixture
+    # nears equilibrium within dt, so the lasting effect is the heat release of the
+    # mole-number-changing reactions, seen in T)
+    shift = max(np.abs(Yo1 - Yo).max(), (np.abs(To1 - To) / To).max())
+    assert shift > 3e-8, shift
     if kernel == 1:
         m4 = synth.config_mechanism(4)
         bx = synth.amr_boxes(m4, 4, synth.config_seed(4), max_cells=24)[3]
