@@ -680,7 +680,15 @@ def test_fp32_lu_refined_matches_fp64(chem, torch_dev):
 def test_fp32_lu_with_kept_matrices(chem, torch_dev):
     """FP32 factors kept across attempts (both options together) against the
     oracle's kept-matrix option at rtol 1e-6, and every result against the
-    oracle's tight-tolerance truth."""
+    oracle's tight-tolerance truth.
+
+    Bar, derived: with kept factors Newton converges linearly and stops at an
+    iterate that carries part of the tolerance, so two correct runs agree only
+    to the integration accuracy, not to rounding.  With eps = max(rtol, the
+    oracle's own kept-matrix distance from the truth) per quantity, both runs
+    lie within eps of the truth when the GPU is as accurate as the oracle, so
+    they agree to 2 eps; the GPU's own distance from the truth is held to the
+    same 2 eps."""
     import oracle
     w = synth.config_workload(1, n=128)
     text = w.mech.to_text()
@@ -696,7 +704,11 @@ def test_fp32_lu_with_kept_matrices(chem, torch_dev):
         f"{eT:.3e}; GPU vs truth {np.abs(Yg - Yt).max():.3e} / {(np.abs(Tg - Tt) / Tt).max():.3e}; "
         f"jacobians {st['n_jac']} of {st['n_attempts']}")
     assert st["rc"] == 0 and st["n_jac"] < 0.5 * st["n_attempts"]
-    assert dY <= TOL_F32 and dT <= TOL_F32
+    barY = 2.0 * max(1e-6, eY)
+    barT = 2.0 * max(1e-6, eT)
+    say(f"lu_fp32 kept: derived bars {barY:.3e} (Y) / {barT:.3e} (T/T)")
+    assert dY <= barY and dT <= barT
+    assert np.abs(Yg - Yt).max() <= barY and (np.abs(Tg - Tt) / Tt).max() <= barT
 
 
 # ------------------------------------------------------------------ serving
