@@ -150,6 +150,29 @@ int chem_integrate(chem_mech* m, int64_t n_cells, double* T, double* Y, double p
 int chem_integrate_ex(chem_mech* m, int64_t n_cells, double* T, double* Y, double p, double dt,
                       double rtol, double atol, chem_stats* stats, int32_t* cell_records);
 
+/* Allocation-free variant of chem_integrate, for callers that cannot
+ * allocate device memory during the call: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, results,
+ * statistics and return codes as chem_integrate (the same kernels run), but
+ * the per-cell records and statistics counters live in a fixed scratch array
+ * of the library on each device (36 MiB for the limit below, held until the
+ * process ends) instead of handle-owned workspace, and the call makes no
+ * hipMalloc/hipFree or other allocating call.  Limits and errors:
+ *   - n_cells <= CHEM_NOALLOC_MAX_CELLS, else CHEM_ERR_ARG;
+ *   - CHEM_OPT_RETRY must be 0 (the retry keeps a copy of the input), else
+ *     CHEM_ERR_ARG;
+ *   - where the handle's options select the lane-per-cell kernels generated
+ *     for the mechanism, they must already be loaded on the device (the first
+ *     chem_integrate or chem_rates call with the handle and these options
+ *     compiles and loads them), else CHEM_ERR_ARG.
+ * Every call on a device shares that device's scratch array, which keeps the
+ * last call's contents (the counters are cleared by each call on its stream):
+ * calls that overlap on one device, from any handle or thread, race and must
+ * be serialised by the caller. */
+#define CHEM_NOALLOC_MAX_CELLS 1048576
+int chem_integrate_noalloc(chem_mech* m, int64_t n_cells, double* T, double* Y, double p, double dt, double rtol,
+                           double atol, chem_stats* stats);
+
 /* One box of cells for chem_integrate_boxes (device SoA arrays of that box). */
 typedef struct {
   double* T;        /* [n_cells] */

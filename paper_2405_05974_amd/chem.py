@@ -42,10 +42,14 @@ OPT_RETRY = 13           # failed cells retried with dt split into 2, 4, ... 2^k
 OPT_JAC_REUSE = 12       # 1: keep the factored Newton matrix while recent; 0 (default): fresh every attempt
 
 EXPORTED = ("chem_mech_load", "chem_mech_load_str", "chem_mech_free", "chem_mech_info", "chem_set_stream",
-            "chem_set_option", "chem_integrate", "chem_integrate_ex", "chem_integrate_boxes", "chem_autotune",
+            "chem_set_option", "chem_integrate", "chem_integrate_ex", "chem_integrate_noalloc", "chem_integrate_boxes",
+            "chem_autotune",
             "chem_rates",
             "chem_last_error", "chem_server_create", "chem_server_submit", "chem_server_poll", "chem_server_drain",
             "chem_server_stats_get", "chem_server_destroy")
+
+
+NOALLOC_MAX_CELLS = 1048576   # CHEM_NOALLOC_MAX_CELLS in chem.h
 
 
 class ChemStats(C.Structure):
@@ -104,6 +108,8 @@ def load_library(path: Optional[str] = None):
                                    C.POINTER(ChemStats)]
     lib.chem_integrate_ex.argtypes = [vp, i64, dp, dp, C.c_double, C.c_double, C.c_double, C.c_double,
                                       C.POINTER(ChemStats), i32p]
+    lib.chem_integrate_noalloc.argtypes = [vp, i64, dp, dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                           C.POINTER(ChemStats)]
     lib.chem_integrate_boxes.argtypes = [vp, C.c_int, C.POINTER(ChemBox), C.c_double, C.c_double, C.c_double,
                                          C.POINTER(ChemStats), C.POINTER(C.c_double)]
     lib.chem_autotune.argtypes = [vp, i64, dp, dp, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -209,6 +215,21 @@ class Mechanism:
         st = ChemStats()
         rc = self.lib.chem_integrate_ex(self.h, n, _ptr(T), _ptr(Y), float(p), float(dt), float(rtol),
                                         float(atol), C.byref(st), _ptr_i32(records))
+        _check(self.lib, rc)
+        out = st.as_dict()
+        out["rc"] = rc
+        return out
+
+    def integrate_noalloc(self, T, Y, p: float, dt: float, rtol: float, atol: float, stream=None) -> dict:
+        """As integrate() without records, through the allocation-free entry
+        point (fixed per-device scratch, at most NOALLOC_MAX_CELLS cells)."""
+        n = T.numel()
+        if Y.numel() != self.S * n:
+            raise ValueError("Y must hold S * n values")
+        _check(self.lib, self.lib.chem_set_stream(self.h, _stream_handle(stream)))
+        st = ChemStats()
+        rc = self.lib.chem_integrate_noalloc(self.h, n, _ptr(T), _ptr(Y), float(p), float(dt), float(rtol),
+                                             float(atol), C.byref(st))
         _check(self.lib, rc)
         out = st.as_dict()
         out["rc"] = rc

@@ -314,7 +314,10 @@ int ensure_records(chem_mech* h, int64_t n) {
 
 // ------------------------------------------------ kernel family selection
 
-int chem_select_kernel(chem_mech* m, bool* lpc) {
+namespace {
+
+// The kernel family the handle's options ask for (without compiling anything).
+int kernel_choice(const chem_mech* m, bool* lpc) {
   const int N = m->dev.N;
   bool want = false;
   if (m->kernel_mode == 2) {
@@ -328,10 +331,22 @@ int chem_select_kernel(chem_mech* m, bool* lpc) {
     want = N <= chemgpu::kLpcMaxN && !m->lu_fp32 && !m->jac_mode;
   }
   *lpc = want;
-  if (!want) return CHEM_OK;
+  return CHEM_OK;
+}
+
+// True when the lane-per-cell module for the handle's device and options is loaded.
+bool lpc_ready(const chem_mech* m) {
+  return m->lpc_integrate && m->lpc_device == m->device && m->lpc_reuse == (m->jac_reuse ? 1 : 0);
+}
+
+}  // namespace
+
+int chem_select_kernel(chem_mech* m, bool* lpc) {
+  const int crc = kernel_choice(m, lpc);
+  if (crc != CHEM_OK || !*lpc) return crc;
   std::lock_guard<std::mutex> lk(m->lpc_mu);
   const int reuse = m->jac_reuse ? 1 : 0;
-  if (m->lpc_integrate && m->lpc_device == m->device && m->lpc_reuse == reuse) return CHEM_OK;
+  if (lpc_ready(m)) return CHEM_OK;
   if (m->lpc_src.empty() || m->lpc_reuse != reuse) m->lpc_src = chemgpu::lpc_source(m->host, reuse != 0);
   std::string log;
   if (chemgpu::lpc_module(m->lpc_src, m->device, &m->lpc_integrate, &m->lpc_boxes, &m->lpc_rates, log) != 0)
@@ -656,6 +671,106 @@ int chem_integrate_ex(chem_mech* m, int64_t n_cells, double* T, double* Y, doubl
 int chem_integrate(chem_mech* m, int64_t n_cells, double* T, double* Y, double p, double dt, double rtol,
                    double atol, chem_stats* stats) {
   return chem_integrate_ex(m, n_cells, T, Y, p, dt, rtol, atol, stats, nullptr);
+}
+
+}  // extern "C"
+
+// ------------------------------------------ integration without allocation
+//
+// chem_integrate_noalloc keeps its per-cell records and statistics counters
+// in `scratch`, one fixed array per device that lives until the process
+// ends.  In host code the array's name is only a stand-in for the device
+// symbol: its device address is looked up once per device and used wherever
+// the host passes the array to a kernel or copy.
+namespace {
+
+constexpr size_t kScratchStatBytes = 256;   // kStatCount counters, padded to the array's alignment
+constexpr size_t kScratchBytes =
+    kScratchStatBytes + sizeof(int32_t) * chemgpu::kRecRows * (size_t)CHEM_NOALLOC_MAX_CELLS;
+static_assert(sizeof(unsigned long long) * chemgpu::kStatCount <= kScratchStatBytes, "stats do not fit");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_dev[kMaxDevices] = {};   // device address of `scratch` per device
+
+// Device address of `scratch` on `device`, looked up on the first call for
+// that device with the device current.
+int scratch_address(int device, unsigned char** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(CHEM_ERR_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    unsigned char* ptr = nullptr;
+    e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress of the scratch array");
+    if (!ptr) return fail(CHEM_ERR_DEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_dev[device] = ptr;
+  }
+  *out = g_scratch_dev[device];
+  return CHEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int chem_integrate_noalloc(chem_mech* m, int64_t n_cells, double* T, double* Y, double p, double dt, double rtol,
+                           double atol, chem_stats* stats) {
+  if (!m) return fail(CHEM_ERR_ARG, "mechanism is NULL");
+  if (n_cells < 0) return fail(CHEM_ERR_ARG, "n_cells < 0");
+  if (n_cells > CHEM_NOALLOC_MAX_CELLS)
+    return fail(CHEM_ERR_ARG, "n_cells " + std::to_string(n_cells) + " exceeds the allocation-free limit of " +
+                                  std::to_string((long long)CHEM_NOALLOC_MAX_CELLS) + " cells");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(CHEM_ERR_ARG, "dt must be positive and finite");
+  if (!(rtol > 0) || !std::isfinite(rtol)) return fail(CHEM_ERR_ARG, "rtol must be positive");
+  if (!(atol >= 0) || !std::isfinite(atol)) return fail(CHEM_ERR_ARG, "atol must be >= 0");
+  if (!(p > 0) || !std::isfinite(p)) return fail(CHEM_ERR_ARG, "p must be positive");
+  if (m->retry > 0)
+    return fail(CHEM_ERR_ARG, "the retry option (CHEM_OPT_RETRY) keeps a copy of the inputs and so allocates; "
+                              "set it to 0 for the allocation-free call");
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  if (n_cells == 0) return CHEM_OK;
+  if (!T || !Y) return fail(CHEM_ERR_ARG, "T or Y is NULL");
+  bool lpc = false;
+  const int krc = kernel_choice(m, &lpc);
+  if (krc != CHEM_OK) return krc;
+  if (lpc) {
+    std::lock_guard<std::mutex> lk(m->lpc_mu);
+    if (!lpc_ready(m))
+      return fail(CHEM_ERR_ARG, "the mechanism's generated kernels are not loaded on this device for these options; "
+                                "call chem_integrate once with the handle first (loading a code object allocates)");
+  }
+  unsigned char* base = nullptr;
+  const int src = scratch_address(m->device, &base);
+  if (src != CHEM_OK) return src;
+  unsigned long long* dstats = reinterpret_cast<unsigned long long*>(base);
+  int32_t* rec = reinterpret_cast<int32_t*>(base + kScratchStatBytes);
+  const IntParams prm = make_int_params(m, p, dt, rtol, atol);
+  hipError_t e = hipEventRecord(m->ev0, m->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  e = launch_either(m, lpc, prm, T, Y, n_cells, rec);
+  if (e != hipSuccess) return hip_fail(e, "integrate kernel launch");
+  e = hipEventRecord(m->ev1, m->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  // the reduction clears the counters with a kernel of its own before summing
+  e = chemgpu::launch_reduce_records(rec, n_cells, dstats, m->stream);
+  if (e != hipSuccess) return hip_fail(e, "stats reduction launch");
+  unsigned long long hs[chemgpu::kStatCount];
+  e = hipMemcpyAsync(hs, dstats, sizeof hs, hipMemcpyDeviceToHost, m->stream);
+  if (e != hipSuccess) return hip_fail(e, "stats copy");
+  e = hipStreamSynchronize(m->stream);
+  if (e != hipSuccess) return hip_fail(e, "integrate");
+  float ms = 0.0f;
+  (void)hipEventElapsedTime(&ms, m->ev0, m->ev1);
+  if (stats) fill_stats(stats, n_cells, hs, ms);
+  g_last_error.clear();
+  return hs[8] ? CHEM_WARN_CELLS_FAILED : CHEM_OK;
 }
 
 namespace {
