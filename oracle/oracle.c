@@ -18,11 +18,13 @@
  * variant and its error control unstated; the readings used here are:
  *   - k_f = exp(ln A + b ln T - (Ea/R)/T); K_c from Gibbs energies with
  *     p0 = 1 atm; k_b = k_f / K_c; third-body reactions multiply both
- *     directions by [M] = sum_k C_k (unit efficiencies); Lindemann falloff
- *     k = k_inf Pr/(1+Pr), Pr = k_0 [M]/k_inf (CHEMKIN theory).
+ *     directions by [M] = sum_k eps_k C_k (efficiencies 1 unless listed);
+ *     Lindemann falloff k = k_inf Pr/(1+Pr), Pr = k_0 [M]/k_inf, optionally
+ *     times Troe's broadening factor (CHEMKIN theory).
  *   - constant-pressure adiabatic reactor, state y = (Y_1..Y_S, T):
  *       dY_k/dt = W_k wdot_k / rho,  dT/dt = -sum_k H_k wdot_k / sum_k C_k Cp_k
- *   - species thermo with linear heat capacity cp/R = a0 + a1 T.
+ *   - species thermo with linear heat capacity cp/R = a0 + a1 T, or NASA
+ *     7-coefficient polynomials in two temperature ranges.
  *   - quasi-constant-step BDF in backward-difference form, orders 1-5, a
  *     factored Newton matrix kept while recent (or fresh every step), WRMS
  *     error control, and after every accepted step projection of Y onto
@@ -52,12 +54,19 @@ static const double ORC_CAL = 4.184;                 /* J/cal */
 static const double ORC_PATM = 101325.0;             /* Pa, standard-state pressure */
 static const double ORC_TREF = 298.15;               /* K, thermo reference */
 
+#define ORC_MAX_EFF 32
+
 typedef struct {
-  int rev, type;             /* type 0 elementary, 1 third body, 2 Lindemann */
+  int rev, type;             /* type 0 elementary, 1 third body, 2 falloff (Lindemann, or Troe when ntroe > 0) */
   int nr, np;
   int r[ORC_MAX_SIDE], p[ORC_MAX_SIDE];
   double A, b, Ea_kcal;
   double A0, b0, Ea0_kcal;   /* falloff low-pressure limit */
+  int ntroe;                 /* 0, or 3/4 Troe parameters alpha, T3, T1 [, T2] (CHEMKIN's T***, T*, T**) */
+  double troe[4];
+  int neff;                  /* collision efficiencies other than 1 in [M] */
+  int effk[ORC_MAX_EFF];
+  double effv[ORC_MAX_EFF];
 } orc_reaction;
 
 typedef struct {
@@ -66,6 +75,8 @@ typedef struct {
   int *atoms;                /* [S][E] */
   int *inert;
   double *W, *a0, *a1, *hf, *s0;
+  int *nasa;                 /* [S] 1: NASA 7-coefficient thermo (nasa_c), 0: linear cp (a0, a1, hf, s0) */
+  double *nasa_c;            /* [S][15]: T_mid, 7 coefficients for T <= T_mid, 7 for T > T_mid */
   orc_reaction *rx;
   int *nu;                   /* [S][R] net stoichiometric coefficient nu'' - nu' */
 } orc_mech;
@@ -111,10 +122,19 @@ static int orc_word(orc_lex *L, const char *w) {
   return orc_next(L, t, sizeof t) && strcmp(t, w) == 0;
 }
 
+/* True (and the word consumed) when the next token is w; otherwise nothing is consumed. */
+static int orc_opt_word(orc_lex *L, const char *w) {
+  orc_lex save = *L;
+  char t[128];
+  if (orc_next(L, t, sizeof t) && strcmp(t, w) == 0) return 1;
+  *L = save;
+  return 0;
+}
+
 void orc_free(orc_mech *m) {
   if (!m) return;
   free(m->atoms); free(m->inert); free(m->W); free(m->a0); free(m->a1);
-  free(m->hf); free(m->s0); free(m->rx); free(m->nu); free(m);
+  free(m->hf); free(m->s0); free(m->nasa); free(m->nasa_c); free(m->rx); free(m->nu); free(m);
 }
 
 /* Parse the mechanism text (format documented with the generator) and derive
@@ -137,6 +157,8 @@ orc_mech *orc_load(const char *text, char *err, int errlen) {
   m->W = calloc(S, sizeof(double)); m->a0 = calloc(S, sizeof(double));
   m->a1 = calloc(S, sizeof(double)); m->hf = calloc(S, sizeof(double));
   m->s0 = calloc(S, sizeof(double));
+  m->nasa = calloc(S, sizeof(int));
+  m->nasa_c = calloc((size_t)S * 15, sizeof(double));
   for (int k = 0; k < S; ++k) {
     if (!orc_next(&L, name, sizeof name) || !orc_int(&L, &m->inert[k])) FAIL("bad species line");
     double W = 0.0;
@@ -148,8 +170,15 @@ orc_mech *orc_load(const char *text, char *err, int errlen) {
     }
     if (tot == 0) FAIL("species without atoms");
     m->W[k] = W;
-    if (!orc_dbl(&L, &m->a0[k]) || !orc_dbl(&L, &m->a1[k]) || !orc_dbl(&L, &m->hf[k]) || !orc_dbl(&L, &m->s0[k]))
+    if (orc_opt_word(&L, "NASA7")) {
+      m->nasa[k] = 1;
+      for (int i = 0; i < 15; ++i)
+        if (!orc_dbl(&L, &m->nasa_c[k * 15 + i])) FAIL("bad NASA7 thermo");
+      if (!(m->nasa_c[k * 15] > 0)) FAIL("bad NASA7 midpoint temperature");
+    } else if (!orc_dbl(&L, &m->a0[k]) || !orc_dbl(&L, &m->a1[k]) || !orc_dbl(&L, &m->hf[k]) ||
+               !orc_dbl(&L, &m->s0[k])) {
       FAIL("bad thermo");
+    }
   }
   if (!orc_word(&L, "REACTIONS") || !orc_int(&L, &m->R) || m->R < 0 || m->R > 100000) FAIL("bad REACTIONS");
   int R = m->R;
@@ -167,6 +196,22 @@ orc_mech *orc_load(const char *text, char *err, int errlen) {
     if (!orc_dbl(&L, &x->A) || !orc_dbl(&L, &x->b) || !orc_dbl(&L, &x->Ea_kcal) || x->A <= 0) FAIL("bad Arrhenius");
     if (x->type == 2 && (!orc_dbl(&L, &x->A0) || !orc_dbl(&L, &x->b0) || !orc_dbl(&L, &x->Ea0_kcal) || x->A0 <= 0))
       FAIL("bad falloff");
+    if (orc_opt_word(&L, "TROE")) {
+      if (x->type != 2 || !orc_int(&L, &x->ntroe) || (x->ntroe != 3 && x->ntroe != 4)) FAIL("bad TROE");
+      for (int i = 0; i < x->ntroe; ++i)
+        if (!orc_dbl(&L, &x->troe[i])) FAIL("bad TROE parameter");
+      if (x->troe[1] == 0.0 || x->troe[2] == 0.0) FAIL("TROE temperatures T3 and T1 must be nonzero");
+    }
+    if (orc_opt_word(&L, "EFF")) {
+      if (x->type == 0 || !orc_int(&L, &x->neff) || x->neff < 0 || x->neff > ORC_MAX_EFF) FAIL("bad EFF");
+      for (int i = 0; i < x->neff; ++i) {
+        if (!orc_int(&L, &x->effk[i]) || x->effk[i] < 0 || x->effk[i] >= S || !orc_dbl(&L, &x->effv[i]) ||
+            x->effv[i] < 0)
+          FAIL("bad efficiency");
+        for (int i2 = 0; i2 < i; ++i2)
+          if (x->effk[i2] == x->effk[i]) FAIL("repeated efficiency");
+      }
+    }
     for (int i = 0; i < x->nr; ++i) m->nu[x->r[i] * R + j] -= 1;
     for (int i = 0; i < x->np; ++i) m->nu[x->p[i] * R + j] += 1;
     for (int e = 0; e < E; ++e) {   /* element balance, exact in integers */
@@ -191,18 +236,68 @@ int orc_nu(const orc_mech *m, int *nu) { memcpy(nu, m->nu, sizeof(int) * m->S * 
 
 /* ---------------------------------------------------------------- thermo -- */
 
+/* Molar enthalpy, entropy, heat capacity and its T-derivative of species k
+ * (J/mol, J/(mol K), J/(mol K^2)).
+ *   linear:  cp/R = a0 + a1 T, integrated from h_f and s0 at 298.15 K;
+ *   NASA 7-coefficient polynomials (the CHEMKIN thermo form of real
+ *   mechanisms), coefficients c1..c7 of the range holding T (T <= T_mid: the
+ *   low range):
+ *     cp/R = c1 + c2 T + c3 T^2 + c4 T^3 + c5 T^4
+ *     H/(R T) = c1 + c2 T/2 + c3 T^2/3 + c4 T^3/4 + c5 T^4/5 + c6/T
+ *     S/R = c1 ln T + c2 T + c3 T^2/2 + c4 T^3/3 + c5 T^4/4 + c7 */
+static void orc_species_thermo(const orc_mech *m, int k, double T, double *h, double *s, double *cp, double *dcp) {
+  if (m->nasa[k]) {
+    const double *c = m->nasa_c + (size_t)k * 15;
+    const double *a = T <= c[0] ? c + 1 : c + 8;
+    double T2 = T * T, T3 = T2 * T, T4 = T3 * T;
+    *cp = ORC_RU * (a[0] + a[1] * T + a[2] * T2 + a[3] * T3 + a[4] * T4);
+    *h = ORC_RU * (a[0] * T + a[1] * T2 / 2.0 + a[2] * T3 / 3.0 + a[3] * T4 / 4.0 + a[4] * T4 * T / 5.0 + a[5]);
+    *s = ORC_RU * (a[0] * log(T) + a[1] * T + a[2] * T2 / 2.0 + a[3] * T3 / 3.0 + a[4] * T4 / 4.0 + a[6]);
+    *dcp = ORC_RU * (a[1] + 2.0 * a[2] * T + 3.0 * a[3] * T2 + 4.0 * a[4] * T3);
+    return;
+  }
+  double a0 = m->a0[k], a1 = m->a1[k];
+  *h = m->hf[k] + ORC_RU * (a0 * (T - ORC_TREF) + a1 * (T * T - ORC_TREF * ORC_TREF) / 2.0);
+  *s = m->s0[k] + ORC_RU * (a0 * log(T / ORC_TREF) + a1 * (T - ORC_TREF));
+  *cp = ORC_RU * (a0 + a1 * T);
+  *dcp = ORC_RU * a1;
+}
+
 /* Per-species molar enthalpy, entropy, heat capacity and Gibbs energy (J/mol,
- * J/(mol K)) for cp/R = a0 + a1 T, integrated from the 298.15 K reference. */
+ * J/(mol K)). */
 void orc_thermo(const orc_mech *m, double T, double *H, double *Sm, double *Cp, double *G) {
   for (int k = 0; k < m->S; ++k) {
-    double a0 = m->a0[k], a1 = m->a1[k];
-    double h = m->hf[k] + ORC_RU * (a0 * (T - ORC_TREF) + a1 * (T * T - ORC_TREF * ORC_TREF) / 2.0);
-    double s = m->s0[k] + ORC_RU * (a0 * log(T / ORC_TREF) + a1 * (T - ORC_TREF));
+    double h, s, cp, dcp;
+    orc_species_thermo(m, k, T, &h, &s, &cp, &dcp);
     if (H) H[k] = h;
     if (Sm) Sm[k] = s;
-    if (Cp) Cp[k] = ORC_RU * (a0 + a1 * T);
+    if (Cp) Cp[k] = cp;
     if (G) G[k] = h - T * s;
   }
+}
+
+/* d Cp_k / dT for every species (J/(mol K^2)). */
+void orc_dcp_dT(const orc_mech *m, double T, double *dCp) {
+  for (int k = 0; k < m->S; ++k) {
+    double h, s, cp;
+    orc_species_thermo(m, k, T, &h, &s, &cp, &dCp[k]);
+  }
+}
+
+/* Third-body concentration of reaction j: [M]_j = sum_k eps_jk C_k, with
+ * eps = 1 except where the reaction lists another efficiency. */
+static double orc_third_body(const orc_mech *m, int j, const double *C, double Mconc) {
+  const orc_reaction *x = &m->rx[j];
+  double M = Mconc;
+  for (int i = 0; i < x->neff; ++i) M += (x->effv[i] - 1.0) * C[x->effk[i]];
+  return M;
+}
+
+/* d[M]_j / dC_c. */
+static double orc_efficiency(const orc_reaction *x, int c) {
+  for (int i = 0; i < x->neff; ++i)
+    if (x->effk[i] == c) return x->effv[i];
+  return 1.0;
 }
 
 /* Mixture: mean molecular weight, density (g/cm^3) and concentrations (mol/cm^3). */
@@ -238,6 +333,44 @@ static orc_k orc_rate_constants(const orc_mech *m, int j, double T, const double
     /* d ln kf/dT = d ln kinf/dT + (d ln Pr/dT)/(1+Pr), d ln Pr/dT = d ln k0 - d ln kinf */
     dlnkf = dlnkinf + (dlnk0 - dlnkinf) / (1.0 + Pr);
     dkf_dM = k0 / ((1.0 + Pr) * (1.0 + Pr));
+    if (x->ntroe) {
+      /* Troe's broadening factor (CHEMKIN form), logarithms base 10:
+       *   F_cent = (1-a) exp(-T/T3) + a exp(-T/T1) [+ exp(-T2/T)]
+       * (T3, T1, T2 are CHEMKIN's T***, T* and T**)
+       *   c = -0.4 - 0.67 log F_cent,  n = 0.75 - 1.27 log F_cent,  d = 0.14
+       *   f1 = (log Pr + c) / (n - d (log Pr + c))
+       *   log F = log F_cent / (1 + f1^2),   k = k_inf Pr/(1+Pr) F
+       * with log Pr taken at max(Pr, 1e-300) so that [M] = 0 stays finite. */
+      const double a = x->troe[0], T3 = x->troe[1], T1 = x->troe[2];
+      double Fc = (1.0 - a) * exp(-T / T3) + a * exp(-T / T1);
+      double dFc = -(1.0 - a) / T3 * exp(-T / T3) - a / T1 * exp(-T / T1);
+      if (x->ntroe == 4) {
+        const double T2 = x->troe[3];
+        Fc += exp(-T2 / T);
+        dFc += T2 / (T * T) * exp(-T2 / T);
+      }
+      const double ln10 = log(10.0);
+      double Lc = log10(Fc);
+      double lp = log10(Pr > 1e-300 ? Pr : 1e-300);
+      double cc = -0.4 - 0.67 * Lc, nn = 0.75 - 1.27 * Lc, dd = 0.14;
+      double u = lp + cc, v = nn - dd * u;
+      double f1 = u / v;
+      double den = 1.0 + f1 * f1;
+      double logF = Lc / den;
+      double F = pow(10.0, logF);
+      /* partial derivatives of log F: in log Pr (L_c fixed) and in L_c (log Pr fixed) */
+      double df1_dlp = nn / (v * v);
+      double df1_dLc = (-0.67 * v - u * (-1.27 + 0.67 * dd)) / (v * v);
+      double dlogF_dlp = -Lc * 2.0 * f1 * df1_dlp / (den * den);
+      double dlogF_dLc = 1.0 / den - Lc * 2.0 * f1 * df1_dLc / (den * den);
+      double dLc_dT = dFc / (Fc * ln10);
+      double dlp_dT = (Pr > 1e-300) ? (dlnk0 - dlnkinf) / ln10 : 0.0;
+      double dlnF_dT = ln10 * (dlogF_dlp * dlp_dT + dlogF_dLc * dLc_dT);
+      /* d F/d[M] = F ln10 dlogF/dlp d lp/d[M] = F dlogF/dlp / [M]; times kinf Pr/(1+Pr) = k0 [M]/(1+Pr) */
+      dkf_dM = F * dkf_dM + F * k0 / (1.0 + Pr) * (Pr > 1e-300 ? dlogF_dlp : 0.0);
+      kf *= F;
+      dlnkf += dlnF_dT;
+    }
   }
   K.kf = kf;
   K.dkf = kf * dlnkf;
@@ -276,12 +409,13 @@ int orc_rates(const orc_mech *m, double T, const double *Y, double p, double *kf
   if (wdot) for (int k = 0; k < S; ++k) wdot[k] = 0.0;
   for (int j = 0; j < R; ++j) {
     const orc_reaction *x = &m->rx[j];
-    orc_k K = orc_rate_constants(m, j, T, G, H, Mconc);
+    double Mj = orc_third_body(m, j, C, Mconc);
+    orc_k K = orc_rate_constants(m, j, T, G, H, Mj);
     double pf = 1.0, pr = 1.0;
     for (int i = 0; i < x->nr; ++i) pf *= C[x->r[i]];
     for (int i = 0; i < x->np; ++i) pr *= C[x->p[i]];
     double q = K.kf * pf - K.kr * pr;
-    if (x->type == 1) q *= Mconc;
+    if (x->type == 1) q *= Mj;
     if (kf) kf[j] = K.kf;
     if (kr) kr[j] = K.kr;
     if (Q) Q[j] = q;
@@ -322,15 +456,15 @@ int orc_jac(const orc_mech *m, const double *y, double p, int fixed_T, double *J
   int S = m->S, R = m->R, N = S + 1;
   double T = y[S];
   double *C = malloc(sizeof(double) * (size_t)(8 * S + S * S + 2 * S * N + N));
-  double *H = C + S, *Cp = H + S, *G = Cp + S, *Sm = G + S, *wd = Sm + S, *b = wd + S, *dum = b + S;
-  double *A = dum + S;              /* [S][S] */
+  double *H = C + S, *Cp = H + S, *G = Cp + S, *Sm = G + S, *wd = Sm + S, *b = wd + S, *dCp = b + S;
+  double *A = dCp + S;              /* [S][S] */
   double *dC = A + S * S;           /* [S][N]: dC_m/dy_j */
   double *dw = dC + S * N;          /* [S][N]: d wdot_k/dy_j */
   double *drho = dw + S * N;        /* [N] */
-  (void)dum;
   double rho, Wbar;
   orc_mixture(m, T, y, p, &rho, &Wbar, C);
   orc_thermo(m, T, H, Sm, Cp, G);
+  orc_dcp_dT(m, T, dCp);
   for (int k = 0; k < S; ++k) G[k] /= ORC_RU * T;
   double Mconc = 0.0;
   for (int k = 0; k < S; ++k) Mconc += C[k];
@@ -338,11 +472,12 @@ int orc_jac(const orc_mech *m, const double *y, double p, int fixed_T, double *J
   for (int k = 0; k < S; ++k) { b[k] = 0.0; wd[k] = 0.0; }
   for (int j = 0; j < R; ++j) {
     const orc_reaction *x = &m->rx[j];
-    orc_k K = orc_rate_constants(m, j, T, G, H, Mconc);
+    double Mj = orc_third_body(m, j, C, Mconc);
+    orc_k K = orc_rate_constants(m, j, T, G, H, Mj);
     double pf = 1.0, pr = 1.0;
     for (int i = 0; i < x->nr; ++i) pf *= C[x->r[i]];
     for (int i = 0; i < x->np; ++i) pr *= C[x->p[i]];
-    double mfac = (x->type == 1) ? Mconc : 1.0;
+    double mfac = (x->type == 1) ? Mj : 1.0;
     double q = mfac * (K.kf * pf - K.kr * pr);
     double dq_dT = mfac * (K.dkf * pf - K.dkr * pr);
     /* dq/dC_c for every species c: product rule over the reactant/product lists */
@@ -361,8 +496,9 @@ int orc_jac(const orc_mech *m, const double *y, double p, int fixed_T, double *J
         dpr += t;
       }
       double dq = mfac * (K.kf * dpf - K.kr * dpr);
-      if (x->type == 1) dq += K.kf * pf - K.kr * pr;             /* d[M]/dC_c = 1 */
-      if (x->type == 2) dq += K.dkf_dM * pf - K.dkr_dM * pr;
+      double eps = (x->type == 0) ? 0.0 : orc_efficiency(x, c);   /* d[M]_j/dC_c */
+      if (x->type == 1) dq += eps * (K.kf * pf - K.kr * pr);
+      if (x->type == 2) dq += eps * (K.dkf_dM * pf - K.dkr_dM * pr);
       for (int k = 0; k < S; ++k) A[k * S + c] += m->nu[k * R + j] * dq;
     }
     for (int k = 0; k < S; ++k) {
@@ -401,7 +537,7 @@ int orc_jac(const orc_mech *m, const double *y, double p, int fixed_T, double *J
     if (j == S)
       for (int k = 0; k < S; ++k) {
         dnum += Cp[k] * wd[k];                       /* dH_k/dT = Cp_k */
-        dden += C[k] * ORC_RU * m->a1[k];            /* dCp_k/dT */
+        dden += C[k] * dCp[k];
       }
     J[S * N + j] = -dnum / den + num * dden / (den * den);
   }
@@ -462,6 +598,25 @@ double orc_enthalpy(const orc_mech *m, double T, const double *Y) {
  * the cancellation-free form T = 2c / (beta + sqrt(beta^2 + 4 gamma c)),
  * c = h - alpha. */
 double orc_temperature_from_h(const orc_mech *m, double h, const double *Y) {
+  int any_nasa = 0;
+  for (int k = 0; k < m->S; ++k) any_nasa |= m->nasa[k];
+  if (any_nasa) {
+    /* Newton on h(T) = h with dh/dT = cp > 0, kept inside a shrinking bracket */
+    double lo = 10.0, hi = 10000.0, T = 1000.0;
+    double *H = malloc(sizeof(double) * 2 * m->S), *Cp = H + m->S;
+    for (int it = 0; it < 200; ++it) {
+      orc_thermo(m, T, H, NULL, Cp, NULL);
+      double g = -h, dg = 0.0;
+      for (int k = 0; k < m->S; ++k) { g += Y[k] * H[k] / m->W[k]; dg += Y[k] * Cp[k] / m->W[k]; }
+      if (g > 0) hi = T; else lo = T;
+      double Tn = T - g / dg;
+      if (!(Tn > lo && Tn < hi)) Tn = 0.5 * (lo + hi);
+      if (fabs(Tn - T) <= 1e-13 * T) { T = Tn; break; }
+      T = Tn;
+    }
+    free(H);
+    return T;
+  }
   double al = 0.0, be = 0.0, ga = 0.0;
   for (int k = 0; k < m->S; ++k) {
     double w = Y[k] / m->W[k];

@@ -36,12 +36,18 @@ Mechanism text format (version 1), one record per line, '#' starts a comment::
     <symbol> <mass g/mol>                                  (E lines)
     SPECIES <S>
     <name> <inert 0|1> <n_e0> .. <n_e(E-1)> <a0> <a1> <hf J/mol> <s0 J/mol/K>
+      or
+    <name> <inert 0|1> <n_e0> .. <n_e(E-1)> NASA7 <T_mid> <c1..c7 for T <= T_mid> <c1..c7 above>
     REACTIONS <R>
     <rev 0|1> <type 0|1|2> <nr> <r_1..r_nr> <np> <p_1..p_np> <A> <b> <Ea kcal/mol> [<A0> <b0> <Ea0>]
+        [TROE <3|4> <alpha> <T3> <T1> [<T2>]] [EFF <n> <k_1> <eps_1> .. <k_n> <eps_n>]
     END
 
-type 0 = elementary, 1 = third body (+M, unit efficiencies), 2 = Lindemann
-falloff (+M) whose low-pressure limit (A0, b0, Ea0) follows.  Reactant and
+type 0 = elementary, 1 = third body (+M), 2 = falloff (+M) whose
+low-pressure limit (A0, b0, Ea0) follows (Lindemann form, times Troe's
+broadening factor when TROE follows; T3, T1, T2 are CHEMKIN's T***, T*, T**).
+EFF lists collision efficiencies other than 1 in [M] for types 1 and 2.
+NASA7 gives CHEMKIN's 7-coefficient polynomials in two ranges split at T_mid.  Reactant and
 product lists hold 0-based species indices, a repeated index meaning a
 stoichiometric coefficient of 2 (at most 3 entries per side).  Floats are
 written with 17 significant digits so that every parser reads back the same
@@ -51,7 +57,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Optional, Sequence, Tuple
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -69,8 +75,10 @@ class Reaction:
     b: float
     Ea: float                 # kcal/mol
     reversible: bool = True
-    kind: int = 0             # 0 elementary, 1 third body, 2 Lindemann falloff
+    kind: int = 0             # 0 elementary, 1 third body, 2 falloff (Lindemann, or Troe with `troe`)
     low: Optional[Tuple[float, float, float]] = None   # (A0, b0, Ea0 kcal/mol)
+    troe: Optional[Tuple[float, ...]] = None           # (alpha, T3, T1[, T2]) of a Troe falloff
+    eff: Optional[Dict[int, float]] = None             # collision efficiencies other than 1
 
 
 @dataclasses.dataclass
@@ -85,6 +93,7 @@ class Mechanism:
     inert: np.ndarray         # [S] bool
     reactions: List[Reaction]
     label: str = ""
+    nasa: Optional[List[Optional[Tuple[float, ...]]]] = None   # per species: (T_mid, 7 low, 7 high) or None
 
     @property
     def n_species(self) -> int:
@@ -110,6 +119,9 @@ def write_mechanism(m: Mechanism) -> str:
     out.append(f"SPECIES {m.n_species}")
     for k, name in enumerate(m.names):
         atoms = " ".join(str(int(v)) for v in m.atoms[k])
+        if m.nasa is not None and m.nasa[k] is not None:
+            out.append(f"{name} {int(bool(m.inert[k]))} {atoms} NASA7 " + " ".join(_f(v) for v in m.nasa[k]))
+            continue
         out.append(f"{name} {int(bool(m.inert[k]))} {atoms} {_f(m.a0[k])} {_f(m.a1[k])} "
                    f"{_f(m.hf[k])} {_f(m.s0[k])}")
     out.append(f"REACTIONS {m.n_reactions}")
@@ -121,6 +133,13 @@ def write_mechanism(m: Mechanism) -> str:
         if r.kind == 2:
             assert r.low is not None
             fields += [_f(v) for v in r.low]
+            if r.troe is not None:
+                fields += ["TROE", str(len(r.troe))] + [_f(v) for v in r.troe]
+        if r.eff:
+            assert r.kind in (1, 2)
+            fields += ["EFF", str(len(r.eff))]
+            for k in sorted(r.eff):
+                fields += [str(int(k)), _f(r.eff[k])]
         out.append(" ".join(fields))
     out.append("END")
     return "\n".join(out) + "\n"
@@ -186,6 +205,82 @@ def make_mechanism(S: int, R: int, E: int, seed: int, max_redraws: int = 1000) -
     names = [f"S{k}" for k in range(S - 1)] + ["INERT"]
     return Mechanism(elements, names, atoms, a0, a1, hf, s0, inert, reactions,
                      label=f"G({S},{R},{E},seed {seed})")
+
+
+# ------------------------------------------- real-mechanism features (f4) ----
+
+TREF = 298.15
+EFF_CHOICES = (0.0, 0.4, 0.7, 2.0, 5.0, 12.0)
+
+
+def nasa7_from_linear(a0: float, a1: float, hf: float, s0: float, c3: float, c4: float, c5: float,
+                      delta: float, t_mid: float = 1000.0) -> Tuple[float, ...]:
+    """NASA 7-coefficient thermo whose low-range cp/R is a0 + a1 T + c3 T^2 +
+    c4 T^3 + c5 T^4, anchored at h_f and s0 (298.15 K), and whose high range
+    adds delta (T - t_mid)^2 to cp/R, with the enthalpy and entropy constants
+    chosen so that cp, H and S are continuous at t_mid.  Polynomial bookkeeping
+    on the coefficient vectors (numpy.polynomial), written once here for the
+    inputs."""
+    P = np.polynomial.polynomial
+    ru = 8.31446261815324
+    cp_lo = np.array([a0, a1, c3, c4, c5])
+    # H/R = int cp/R dT + c6;   S/R = c1 ln T + int (cp/R - c1)/T dT + c7
+    h_poly = P.polyint(cp_lo)                      # zero constant term
+    s_poly = P.polyint(cp_lo[1:])                  # of (cp/R - c1)/T
+    c6 = hf / ru - P.polyval(TREF, h_poly)
+    c7 = s0 / ru - (cp_lo[0] * math.log(TREF) + P.polyval(TREF, s_poly))
+    shift = delta * np.array([t_mid * t_mid, -2.0 * t_mid, 1.0, 0.0, 0.0])   # delta (T - t_mid)^2
+    cp_hi = cp_lo + shift
+    h_hi = P.polyint(cp_hi)
+    s_hi = P.polyint(cp_hi[1:])
+    c6_hi = (P.polyval(t_mid, h_poly) + c6) - P.polyval(t_mid, h_hi)
+    c7_hi = (cp_lo[0] * math.log(t_mid) + P.polyval(t_mid, s_poly) + c7) - \
+        (cp_hi[0] * math.log(t_mid) + P.polyval(t_mid, s_hi))
+    return (float(t_mid), *map(float, cp_lo), float(c6), float(c7), *map(float, cp_hi), float(c6_hi), float(c7_hi))
+
+
+def make_real_mechanism(S: int, R: int, E: int, seed: int, troe_fraction: float = 0.1) -> Mechanism:
+    """G(S,R,E,seed) with the features of real (CHEMKIN/Cantera) mechanisms
+    added from a second stream seeded seed + 7919, leaving G's own draws as
+    they are:
+
+    * every species gets NASA 7-coefficient thermo: the low range adds
+      c3 T^2 + c4 T^3 + c5 T^4 (c3 ~ U[-5e-8, 5e-8], c4 ~ U[-5e-12, 5e-12],
+      c5 ~ U[-5e-16, 5e-16]) to G's linear cp/R, the range splits at 1000 K,
+      and the high range adds delta (T - 1000)^2 with delta ~ U[-1e-7, 1e-7],
+      continuous in cp, H and S;
+    * round(troe_fraction R) elementary reactions become Troe falloff
+      reactions: A0 = A 10^U[3,7], b0 ~ U[-2, 0], Ea0 = Ea U[0, 1]; alpha ~
+      U[0.1, 0.9], T3 ~ U[30, 500] K, T1 ~ U[500, 5000] K, and with
+      probability 1/2 T2 ~ U[1000, 8000] K;
+    * every third-body and falloff reaction lists efficiencies for 3 distinct
+      species drawn uniformly, each from {0, 0.4, 0.7, 2, 5, 12}."""
+    m = make_mechanism(S, R, E, seed)
+    rng = np.random.default_rng(seed + 7919)
+    nasa = []
+    for k in range(S):
+        c3, c4, c5 = rng.uniform(-5e-8, 5e-8), rng.uniform(-5e-12, 5e-12), rng.uniform(-5e-16, 5e-16)
+        delta = rng.uniform(-1e-7, 1e-7)
+        nasa.append(nasa7_from_linear(m.a0[k], m.a1[k], m.hf[k], m.s0[k], c3, c4, c5, delta))
+    m.nasa = nasa
+    elementary = [j for j, r in enumerate(m.reactions) if r.kind == 0]
+    n_troe = min(len(elementary), int(round(troe_fraction * R)))
+    troe_ids = sorted(int(j) for j in rng.choice(elementary, size=n_troe, replace=False)) if n_troe else []
+    for j in troe_ids:
+        r = m.reactions[j]
+        r.kind = 2
+        r.low = (float(r.A * 10.0 ** rng.uniform(3.0, 7.0)), float(rng.uniform(-2.0, 0.0)),
+                 float(r.Ea * rng.uniform(0.0, 1.0)))
+        troe = [float(rng.uniform(0.1, 0.9)), float(rng.uniform(30.0, 500.0)), float(rng.uniform(500.0, 5000.0))]
+        if rng.uniform() < 0.5:
+            troe.append(float(rng.uniform(1000.0, 8000.0)))
+        r.troe = tuple(troe)
+    for r in m.reactions:
+        if r.kind in (1, 2):
+            ks = rng.choice(S, size=min(3, S), replace=False)
+            r.eff = {int(k): float(EFF_CHOICES[int(rng.integers(0, len(EFF_CHOICES)))]) for k in ks}
+    m.label = f"G_real({S},{R},{E},seed {seed})"
+    return m
 
 
 # ---------------------------------------------------------------- states ----

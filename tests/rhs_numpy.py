@@ -12,15 +12,49 @@ TREF = 298.15
 PATM = 101325.0
 
 
+def species_thermo(mech, T):
+    """H, S, Cp per species (J/mol, J/(mol K)); complex T allowed."""
+    S = mech.n_species
+    a0, a1, hf, s0 = mech.a0, mech.a1, mech.hf, mech.s0
+    H = hf + RU * (a0 * (T - TREF) + a1 * (T ** 2 - TREF ** 2) / 2)
+    Sm = s0 + RU * (a0 * np.log(T / TREF) + a1 * (T - TREF))
+    Cp = RU * (a0 + a1 * T)
+    if mech.nasa is None:
+        return H, Sm, Cp
+    H = np.array(H, dtype=complex if np.iscomplexobj(T) else float)
+    Sm = np.array(Sm, dtype=H.dtype)
+    Cp = np.array(Cp, dtype=H.dtype)
+    for k in range(S):
+        if mech.nasa[k] is None:
+            continue
+        c = np.asarray(mech.nasa[k], dtype=float)
+        a = c[1:8] if np.real(T) <= c[0] else c[8:15]
+        powers = np.array([T ** i for i in range(5)])                 # 1, T, .., T^4
+        Cp[k] = RU * np.dot(a[:5], powers)
+        H[k] = RU * (np.dot(a[:5] / np.arange(1, 6), powers * T) + a[5])
+        Sm[k] = RU * (a[0] * np.log(T) + np.dot(a[1:5] / np.arange(1, 5), powers[1:]) + a[6])
+    return H, Sm, Cp
+
+
+def troe_factor(troe, T, Pr):
+    alpha, T3, T1 = troe[0], troe[1], troe[2]
+    Fc = (1 - alpha) * np.exp(-T / T3) + alpha * np.exp(-T / T1)
+    if len(troe) == 4:
+        Fc = Fc + np.exp(-troe[3] / T)
+    logFc = np.log10(Fc)
+    c = -0.4 - 0.67 * logFc
+    n = 0.75 - 1.27 * logFc
+    x = np.log10(Pr) + c
+    f1 = x / (n - 0.14 * x)
+    return 10.0 ** (logFc / (1 + f1 * f1))
+
+
 def rhs(mech, y, p, fixed_T=False):
     S = mech.n_species
     Y = y[:S]
     T = y[S]
     W = mech.atoms @ np.array([m for _, m in mech.elements])
-    a0, a1, hf, s0 = mech.a0, mech.a1, mech.hf, mech.s0
-    H = hf + RU * (a0 * (T - TREF) + a1 * (T ** 2 - TREF ** 2) / 2)
-    Sm = s0 + RU * (a0 * np.log(T / TREF) + a1 * (T - TREF))
-    Cp = RU * (a0 + a1 * T)
+    H, Sm, Cp = species_thermo(mech, T)
     G = H - T * Sm
     # density in g/cm^3 and concentrations in mol/cm^3
     Wbar = 1.0 / np.sum(Y / W)
@@ -29,13 +63,19 @@ def rhs(mech, y, p, fixed_T=False):
     M = np.sum(C)
     wdot = np.zeros(S, dtype=np.result_type(y, float))
     for r in mech.reactions:
+        eps = np.ones(S)
+        for k, e in (r.eff or {}).items():
+            eps[k] = e
+        Mr = np.dot(eps, C)
         kinf = r.A * T ** r.b * np.exp(-r.Ea * 4184.0 / (RU * T))
         kf = kinf
         if r.kind == 2:
             A0, b0, Ea0 = r.low
             k0 = A0 * T ** b0 * np.exp(-Ea0 * 4184.0 / (RU * T))
-            Pr = k0 * M / kinf
+            Pr = k0 * Mr / kinf
             kf = kinf * Pr / (1 + Pr)
+            if r.troe is not None:
+                kf = kf * troe_factor(r.troe, T, Pr)
         pf = np.prod([C[i] for i in r.reactants])
         pr = np.prod([C[i] for i in r.products])
         if r.reversible:
@@ -51,7 +91,7 @@ def rhs(mech, y, p, fixed_T=False):
         else:
             q = kf * pf
         if r.kind == 1:
-            q = q * M
+            q = q * Mr
         for i in r.reactants:
             wdot[i] -= q
         for i in r.products:

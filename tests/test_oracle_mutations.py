@@ -173,9 +173,164 @@ def pin_difference_quotient(lib):
     return bool(np.linalg.norm(Jfd - Jcs) / np.linalg.norm(Jcs) < 1e-5)
 
 
+# -------------------------------------------- real-mechanism features (f4)
+
+def nasa_species_mech(c3=2e-8, c4=-3e-12, c5=2e-16, delta=6e-8):
+    """Two isomers with NASA 7-coefficient thermo whose two ranges differ."""
+    sp = [("A", (2, 1), 3.5, 2e-4, 1000.0, 200.0, False),
+          ("B", (2, 1), 4.1, 1e-4, -5000.0, 210.0, False),
+          ("N", (0, 2), 3.0, 1e-4, 0.0, 190.0, True)]
+    m = mechs.tiny(sp, [synth.Reaction([0], [1], 1e6, 0.5, 5.0, True, 0)])
+    m.nasa = [synth.nasa7_from_linear(m.a0[k], m.a1[k], m.hf[k], m.s0[k], c3, c4, c5, delta) for k in range(3)]
+    return m
+
+
+def pin_nasa_continuity(lib):
+    """cp, H and S continuous at T_mid with differing ranges; dH/dT = cp and
+    dS/dT = cp/T on both sides (Richardson-extrapolated central differences)."""
+    om = oracle.Mech(nasa_species_mech().to_text(), lib_path=lib)
+    Tm = 1000.0
+    below = om.thermo(Tm)                  # T <= T_mid: the low range
+    above = om.thermo(Tm * (1 + 1e-15))
+    for a, b in zip(below[:3], above[:3]):
+        if not np.allclose(a, b, rtol=1e-12, atol=0):
+            return False
+    for T in (600.0, 1700.0):
+        def d(i, h):
+            return (om.thermo(T + h)[i] - om.thermo(T - h)[i]) / (2 * h)
+        dH = (4 * d(0, 0.05) - d(0, 0.1)) / 3
+        dS = (4 * d(1, 0.05) - d(1, 0.1)) / 3
+        _, _, Cp, _ = om.thermo(T)
+        if not (np.allclose(dH, Cp, rtol=1e-8) and np.allclose(dS, Cp / T, rtol=1e-8)):
+            return False
+    return True
+
+
+def pin_nasa_reference(lib):
+    """The low range holds the 298.15 K anchors the coefficients were built
+    on: H = h_f and S = s0 there (the high range differs at 298.15 K)."""
+    m = nasa_species_mech()
+    om = oracle.Mech(m.to_text(), lib_path=lib)
+    H, Sm, _, _ = om.thermo(298.15)
+    return bool(np.allclose(H, m.hf, rtol=0, atol=1e-8) and np.allclose(Sm, m.s0, rtol=0, atol=1e-11))
+
+
+def pin_troe_complex_step(lib):
+    """Jacobian of a Troe falloff pair against complex-step derivatives of the
+    numpy rhs across the falloff range (Pr from ~1e-3 to ~1e3)."""
+    m = troe_pair((0.6, 200.0, 2500.0, 5000.0), eff={2: 3.0})
+    om = oracle.Mech(m.to_text(), lib_path=lib)
+    y = np.array([0.2, 0.1, 0.7, 1300.0])
+    for p in (1e2, 1e4, 1e6, 1e8):
+        Jcs = rhs_numpy.jac_complex_step(m, y, p)
+        J = om.jac(y, p)
+        row = np.abs(J - Jcs).max(axis=1) / np.maximum(np.abs(Jcs).max(axis=1), 1e-300)
+        if row.max() > 1e-9:
+            return False
+    return True
+
+
+def pin_nasa_reduces_to_linear(lib):
+    """NASA polynomials built from a linear cp (c3 = c4 = c5 = delta = 0) give
+    the linear species' H, S and cp on both ranges."""
+    m = nasa_species_mech(0.0, 0.0, 0.0, 0.0)
+    lin = nasa_species_mech()
+    lin.nasa = None
+    om, ol = oracle.Mech(m.to_text(), lib_path=lib), oracle.Mech(lin.to_text(), lib_path=lib)
+    for T in (300.0, 999.0, 1500.0, 2600.0):
+        for a, b in zip(om.thermo(T)[:3], ol.thermo(T)[:3]):
+            if not np.allclose(a, b, rtol=1e-12, atol=1e-9):
+                return False
+    return True
+
+
+def troe_pair(troe, low=(1e12, -0.5, 2.0), eff=None):
+    m = mechs.isomer_pair(A=2e5, b=0.3, Ea=6.0, kind=2, low=low)
+    m.reactions[0].troe = troe
+    m.reactions[0].eff = eff
+    return m
+
+
+def pin_troe_center_and_limits(lib):
+    """Troe's blending at points where its shape function f1 is known
+    exactly: F = F_cent where log10 Pr = -c (f1 = 0, the centre of the
+    falloff curve); f1 = 1/d where log10 Pr + c = n/(2d); f1 = -1/(1+d)
+    where log10 Pr + c = -n (log F = log F_cent / (1 + f1^2)); and F_cent = 1
+    reduces it to the Lindemann form bit for bit."""
+    T = 1300.0
+    troe = (0.6, 200.0, 2500.0, 5000.0)
+    Fc = 0.4 * math.exp(-T / 200.0) + 0.6 * math.exp(-T / 2500.0) + math.exp(-5000.0 / T)
+    kinf = mechs.kf_arrhenius(2e5, 0.3, 6.0, T)
+    k0 = mechs.kf_arrhenius(1e12, -0.5, 2.0, T)
+    om = oracle.Mech(troe_pair(troe).to_text(), lib_path=lib)
+    Y = np.array([0.2, 0.1, 0.7])
+
+    def kf_at(Pr):
+        conc = Pr * kinf / k0                      # [M] in mol/cm^3 (unit efficiencies)
+        p = conc * 1e6 * RU * T
+        return om.rates(T, Y, p)[0][0], conc
+    c = -0.4 - 0.67 * math.log10(Fc)
+    Pr_c = 10.0 ** (-c)
+    kc, _ = kf_at(Pr_c)
+    if abs(kc / (kinf * Pr_c / (1 + Pr_c) * Fc) - 1) > 1e-12:
+        return False
+    n = 0.75 - 1.27 * math.log10(Fc)
+    for u, f1 in ((n / (2 * 0.14), 1 / 0.14), (-n, -1 / 1.14)):
+        Pr = 10.0 ** (u - c)
+        k, _ = kf_at(Pr)
+        if abs(k / (kinf * Pr / (1 + Pr) * Fc ** (1.0 / (1.0 + f1 * f1))) - 1) > 1e-11:
+            return False
+    flat = oracle.Mech(troe_pair((0.0, 1e300, 1.0)).to_text(), lib_path=lib)
+    lind = oracle.Mech(troe_pair(None).to_text(), lib_path=lib)
+    p = 3e5
+    return bool(flat.rates(T, Y, p)[0][0] == lind.rates(T, Y, p)[0][0])
+
+
+def pin_efficiency_decay(lib):
+    """Irreversible third-body A -> B at fixed T with the inert colliding at
+    efficiency 5 and B at 0: Y_A decays as exp(-k_f [M] t) with
+    [M] = C_A + 5 C_N, both constant in time."""
+    T = 1200.0
+    m = mechs.isomer_pair(A=1e10, b=0.0, Ea=3.0, kind=1)
+    m.reactions[0].eff = {1: 0.0, 2: 5.0}
+    om = oracle.Mech(m.to_text(), lib_path=lib)
+    W = om.weights()
+    Y0 = np.array([0.25, 0.05, 0.70])
+    rho = P * 10.0 / (RU * 1e7 * T) / np.sum(Y0 / W)
+    CA, CN = rho * Y0[0] / W[0], rho * Y0[2] / W[2]
+    # [M] changes as A turns into B (efficiency 1 -> 0): solve dCA/dt = -k CA (CA + 5 CN) in closed form
+    k = mechs.kf_arrhenius(1e10, 0.0, 3.0, T)
+    a = 5.0 * CN
+    t = 2.0 / (k * (CA + a))
+    CA_t = a * CA * math.exp(-k * a * t) / (a + CA * (1 - math.exp(-k * a * t)))
+    _, Y1, st = om.integrate(np.array([T]), Y0[:, None], P, t, 1e-12, 1e-20, fixed_T=True)
+    return st[0]["status"] == 0 and abs(Y1[0, 0] / (CA_t * W[0] / rho) - 1) < 1e-8
+
+
+def pin_real_complex_step(lib):
+    """The analytic Jacobian of a mechanism with NASA thermo, Troe falloff and
+    efficiencies against complex-step derivatives of the numpy rhs, on both
+    thermo ranges and at two pressures."""
+    m = synth.make_real_mechanism(12, 40, 4, 5)
+    om = oracle.Mech(m.to_text(), lib_path=lib)
+    rng = np.random.default_rng(11)
+    for T in (750.0, 1600.0):
+        y = np.concatenate([synth.composition(rng, m.n_species, 1.0, 1)[:, 0], [T]])
+        for p in (P, 6e6):
+            f_or = om.rhs(y, p)
+            if not np.allclose(rhs_numpy.rhs(m, y, p), f_or, rtol=1e-10, atol=1e-12 * np.abs(f_or).max()):
+                return False
+            Jcs = rhs_numpy.jac_complex_step(m, y, p)
+            J = om.jac(y, p)
+            row = np.abs(J - Jcs).max(axis=1) / np.maximum(np.abs(Jcs).max(axis=1), 1e-300)
+            if row.max() > 1e-9:
+                return False
+    return True
+
+
 MUTATIONS = [
     ("standard-state exponent sign", "pow(c0, (double)dnu)", "pow(c0, (double)-dnu)", pin_gibbs_minimum),
-    ("third body drops [M]", "if (x->type == 1) q *= Mconc;", "if (x->type == 9) q *= Mconc;",
+    ("third body drops [M]", "if (x->type == 1) q *= Mj;", "if (x->type == 9) q *= Mj;",
      lambda lib: pin_decay(lib, "third_body")),
     ("Lindemann blend", "kf = kinf * Pr / (1.0 + Pr);", "kf = kinf * Pr;",
      lambda lib: pin_decay(lib, "falloff")),
@@ -183,7 +338,7 @@ MUTATIONS = [
      "+ m->W[k] * wd[k] / (rho * rho) * drho[j];", pin_complex_step),
     ("T-column derivative of K_c", "double dlnKc = sumH / (ORC_RU * T * T) - dnu / T;",
      "double dlnKc = sumH / (ORC_RU * T * T);", pin_complex_step),
-    ("entropy temperature term", "a1 * (T - ORC_TREF));\n    if (H)", "a1 * T);\n    if (H)", pin_thermo_reference),
+    ("entropy temperature term", "a1 * (T - ORC_TREF));\n  *cp", "a1 * T);\n  *cp", pin_thermo_reference),
     ("LU without pivoting", "if (fabs(a[i * n + k]) > best)", "if (0 && fabs(a[i * n + k]) > best)", pin_lu),
     ("BDF psi coefficients", "ss += g[j] * D[j][i];", "ss += g[k] * D[j][i];", pin_radau),
     ("enthalpy inversion sign", "double c = h - al;", "double c = al - h;", pin_enthalpy_inversion),
@@ -191,6 +346,21 @@ MUTATIONS = [
      pin_enthalpy_conservation),
     ("difference quotient off by the increment", "ytmp[j] = y[j] + inc;", "ytmp[j] = y[j] + 2.0 * inc;",
      pin_difference_quotient),
+    ("NASA ranges swapped", "T <= c[0] ? c + 1 : c + 8;", "T <= c[0] ? c + 8 : c + 1;", pin_nasa_reference),
+    ("NASA enthalpy constant dropped", "a[4] * T4 * T / 5.0 + a[5]);", "a[4] * T4 * T / 5.0);",
+     pin_nasa_continuity),
+    ("NASA entropy log term", "*s = ORC_RU * (a[0] * log(T) +", "*s = ORC_RU * (a[0] * T +",
+     pin_nasa_reduces_to_linear),
+    ("Troe centre offset sign", "double cc = -0.4 - 0.67 * Lc", "double cc = -0.4 + 0.67 * Lc",
+     pin_troe_center_and_limits),
+    ("Troe derivative in log Pr", "double df1_dlp = nn / (v * v);", "double df1_dlp = 1.0 / v;",
+     pin_troe_complex_step),
+    ("efficiency offset", "M += (x->effv[i] - 1.0) * C[x->effk[i]];", "M += x->effv[i] * C[x->effk[i]];",
+     pin_efficiency_decay),
+    ("efficiency in the Jacobian", "double eps = (x->type == 0) ? 0.0 : orc_efficiency(x, c);",
+     "double eps = (x->type == 0) ? 0.0 : 1.0;", pin_real_complex_step),
+    ("heat-capacity slope in the T row", "dden += C[k] * dCp[k];", "dden += 0.0 * dCp[k];",
+     pin_real_complex_step),
 ]
 
 
