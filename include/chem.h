@@ -104,10 +104,12 @@ typedef struct {
                                    a fresh Jacobian and LU every attempt */
 
 /* Parse a mechanism from a file path / from text (format "chem-mech 1":
- * elements with masses; species with atom counts, inert flag and linear
- * heat capacity cp/R = a0 + a1 T plus formation enthalpy and entropy at
- * 298.15 K; reactions of Eq. 1 with Arrhenius parameters, optional third
- * body (unit efficiencies) or Lindemann falloff).  Validates exact atom
+ * elements with masses; species with atom counts, inert flag and either a
+ * linear heat capacity cp/R = a0 + a1 T plus formation enthalpy and entropy
+ * at 298.15 K, or NASA 7-coefficient polynomials in two temperature ranges
+ * (the CHEMKIN thermo form of real mechanisms); reactions of Eq. 1 with
+ * Arrhenius parameters, optional third body or falloff (Lindemann, or Troe
+ * with 3 or 4 parameters), with collision efficiencies).  Validates exact atom
  * balance of every reaction and uploads the tables to the current device.
  * On success *out receives a new handle.  Errors: CHEM_ERR_ARG (null
  * pointers, unreadable file), CHEM_ERR_PARSE, CHEM_ERR_UNSUPPORTED,

@@ -18,13 +18,28 @@ struct HostReaction {
   std::vector<int> reac, prod;
   double A = 0, b = 0, Ea = 0;      // Ea in kcal/mol
   double A0 = 0, b0 = 0, Ea0 = 0;
+  int ntroe = 0;                    // 0, or 3/4 Troe parameters alpha, T3, T1 [, T2]
+  double troe[4] = {0, 0, 0, 0};
+  std::vector<int> eff_k;           // collision efficiencies other than 1 in [M]
+  std::vector<double> eff_v;
 };
 
 struct HostMech {
   std::vector<double> emass;
   std::vector<std::vector<int>> atoms;  // [S][E]
   std::vector<double> W, a0, a1, hf, s0;
+  // NASA 7-coefficient thermo per species: T_mid, c1..c7 (T <= T_mid), c1..c7
+  // above; empty when the species uses the linear cp form
+  std::vector<std::vector<double>> nasa;
   std::vector<HostReaction> rx;
+  bool any_nasa() const {
+    for (const auto& v : nasa)
+      if (!v.empty()) return true;
+    return false;
+  }
+  // The species' NASA coefficients; a linear-cp species written in that form
+  // (both ranges equal: c1 = a0, c2 = a1, c6 and c7 from h_f and s0 at 298.15 K).
+  std::vector<double> nasa_of(int k) const;
 };
 
 }  // namespace chemgpu

@@ -71,11 +71,38 @@ class Tokens {
     return end != t.c_str() && !*end && std::isfinite(v);
   }
   bool skip() { return pos_++ < toks_.size(); }
+  // consume the next token only when it equals w
+  bool opt_word(const char* w) {
+    if (pos_ < toks_.size() && toks_[pos_] == w) {
+      ++pos_;
+      return true;
+    }
+    return false;
+  }
 
  private:
   std::vector<std::string> toks_;
   size_t pos_ = 0;
 };
+
+}  // namespace
+
+std::vector<double> chemgpu::HostMech::nasa_of(int k) const {
+  if (!nasa[k].empty()) return nasa[k];
+  const double Tr = chemgpu::kTref, R = chemgpu::kRu;
+  std::vector<double> c(15, 0.0);
+  c[0] = 1000.0;
+  for (int r = 0; r < 2; ++r) {
+    double* a = &c[1 + 7 * r];
+    a[0] = a0[k];
+    a[1] = a1[k];
+    a[5] = hf[k] / R - (a0[k] * Tr + a1[k] * Tr * Tr * 0.5);
+    a[6] = s0[k] / R - (a0[k] * std::log(Tr) + a1[k] * Tr);
+  }
+  return c;
+}
+
+namespace {
 
 int parse_mechanism(const std::string& text, HostMech& m) {
   Tokens tk(text);
@@ -88,6 +115,7 @@ int parse_mechanism(const std::string& text, HostMech& m) {
   if (!tk.word("SPECIES") || !tk.integer(S) || S < 1) return fail(CHEM_ERR_PARSE, "bad SPECIES block");
   m.atoms.assign(S, std::vector<int>(E, 0));
   m.W.resize(S); m.a0.resize(S); m.a1.resize(S); m.hf.resize(S); m.s0.resize(S);
+  m.nasa.assign(S, {});
   for (int k = 0; k < S; ++k) {
     int inert = 0, total = 0;
     if (!tk.skip() || !tk.integer(inert)) return fail(CHEM_ERR_PARSE, "bad species line");
@@ -99,8 +127,14 @@ int parse_mechanism(const std::string& text, HostMech& m) {
     }
     if (total == 0) return fail(CHEM_ERR_PARSE, "species without atoms");
     m.W[k] = w;
-    if (!tk.real(m.a0[k]) || !tk.real(m.a1[k]) || !tk.real(m.hf[k]) || !tk.real(m.s0[k]))
+    if (tk.opt_word("NASA7")) {
+      m.nasa[k].resize(15);
+      for (int i = 0; i < 15; ++i)
+        if (!tk.real(m.nasa[k][i])) return fail(CHEM_ERR_PARSE, "bad NASA7 thermo of species " + std::to_string(k));
+      if (!(m.nasa[k][0] > 0)) return fail(CHEM_ERR_PARSE, "bad NASA7 midpoint temperature");
+    } else if (!tk.real(m.a0[k]) || !tk.real(m.a1[k]) || !tk.real(m.hf[k]) || !tk.real(m.s0[k])) {
       return fail(CHEM_ERR_PARSE, "bad species thermo");
+    }
   }
   if (!tk.word("REACTIONS") || !tk.integer(R) || R < 0) return fail(CHEM_ERR_PARSE, "bad REACTIONS block");
   m.rx.resize(R);
@@ -121,6 +155,29 @@ int parse_mechanism(const std::string& text, HostMech& m) {
       return fail(CHEM_ERR_PARSE, "bad Arrhenius parameters in reaction " + std::to_string(j));
     if (x.type == 2 && (!tk.real(x.A0) || !tk.real(x.b0) || !tk.real(x.Ea0) || !(x.A0 > 0)))
       return fail(CHEM_ERR_PARSE, "bad falloff parameters in reaction " + std::to_string(j));
+    if (tk.opt_word("TROE")) {
+      if (x.type != 2 || !tk.integer(x.ntroe) || (x.ntroe != 3 && x.ntroe != 4))
+        return fail(CHEM_ERR_PARSE, "bad TROE record in reaction " + std::to_string(j));
+      for (int i = 0; i < x.ntroe; ++i)
+        if (!tk.real(x.troe[i])) return fail(CHEM_ERR_PARSE, "bad TROE parameter in reaction " + std::to_string(j));
+      if (x.troe[1] == 0.0 || x.troe[2] == 0.0)
+        return fail(CHEM_ERR_PARSE, "TROE temperatures T3 and T1 must be nonzero");
+    }
+    if (tk.opt_word("EFF")) {
+      int ne = 0;
+      if (x.type == 0 || !tk.integer(ne) || ne < 0 || ne > 64)
+        return fail(CHEM_ERR_PARSE, "bad EFF record in reaction " + std::to_string(j));
+      for (int i = 0; i < ne; ++i) {
+        int k = -1;
+        double v = 0.0;
+        if (!tk.integer(k) || k < 0 || k >= S || !tk.real(v) || !(v >= 0))
+          return fail(CHEM_ERR_PARSE, "bad efficiency in reaction " + std::to_string(j));
+        for (int k2 : x.eff_k)
+          if (k2 == k) return fail(CHEM_ERR_PARSE, "repeated efficiency in reaction " + std::to_string(j));
+        x.eff_k.push_back(k);
+        x.eff_v.push_back(v);
+      }
+    }
     for (int e = 0; e < E; ++e) {
       int bal = 0;
       for (int s : x.prod) bal += m.atoms[s][e];
@@ -144,6 +201,8 @@ int upload(chem_mech* h) {
   const int widths[3] = {16, 32, 64};
 
   std::vector<RxParams> rx(std::max(R, 1));
+  std::vector<int> effk;
+  std::vector<double> effv;
   const double kcal_to_K = 4184.0 / chemgpu::kRu;   // Ea/R per kcal/mol
   for (int j = 0; j < R; ++j) {
     const HostReaction& x = m.rx[j];
@@ -156,6 +215,14 @@ int upload(chem_mech* h) {
       d.lnA0 = std::log(x.A0);
       d.b0 = x.b0;
       d.EaR0 = x.Ea0 * kcal_to_K;
+    }
+    d.ntroe = x.ntroe;
+    for (int i = 0; i < 4; ++i) d.troe[i] = x.troe[i];
+    d.eff_off = (int)effk.size();
+    d.eff_n = (int)x.eff_k.size();
+    for (size_t i = 0; i < x.eff_k.size(); ++i) {
+      effk.push_back(x.eff_k[i]);
+      effv.push_back(x.eff_v[i] - 1.0);
     }
     d.type = x.type;
     d.rev = x.rev;
@@ -212,7 +279,18 @@ int upload(chem_mech* h) {
   const size_t sz_off = align(sizeof(int) * off.size());
   const size_t o_ent = o_off + sz_off;
   const size_t sz_ent = align(sizeof(int) * ent.size());
-  const size_t total = o_ent + sz_ent;
+  const bool nasa = m.any_nasa();
+  const size_t o_nasa = o_ent + sz_ent;
+  const size_t sz_nasa = nasa ? align(sizeof(double) * 15 * S) : 0;
+  if (effk.empty()) {
+    effk.push_back(0);
+    effv.push_back(0.0);
+  }
+  const size_t o_effk = o_nasa + sz_nasa;
+  const size_t sz_effk = align(sizeof(int) * effk.size());
+  const size_t o_effv = o_effk + sz_effk;
+  const size_t sz_effv = align(sizeof(double) * effv.size());
+  const size_t total = o_effv + sz_effv;
   std::vector<char> blob(total, 0);
   double* sp = reinterpret_cast<double*>(blob.data() + o_sp);
   for (int k = 0; k < S; ++k) {
@@ -225,6 +303,15 @@ int upload(chem_mech* h) {
   std::memcpy(blob.data() + o_rx, rx.data(), sizeof(RxParams) * rx.size());
   std::memcpy(blob.data() + o_off, off.data(), sizeof(int) * off.size());
   std::memcpy(blob.data() + o_ent, ent.data(), sizeof(int) * ent.size());
+  if (nasa) {
+    double* nc = reinterpret_cast<double*>(blob.data() + o_nasa);
+    for (int k = 0; k < S; ++k) {
+      const std::vector<double> c = m.nasa_of(k);
+      for (int i = 0; i < 15; ++i) nc[(size_t)i * S + k] = c[i];
+    }
+  }
+  std::memcpy(blob.data() + o_effk, effk.data(), sizeof(int) * effk.size());
+  std::memcpy(blob.data() + o_effv, effv.data(), sizeof(double) * effv.size());
 
   hipError_t e = hipGetDevice(&h->device);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -254,6 +341,10 @@ int upload(chem_mech* h) {
   dm.csr_off = h->csr_off_np[np == 16 ? 0 : (np == 32 ? 1 : 2)];
   dm.nch = h->nch_np[np == 16 ? 0 : (np == 32 ? 1 : 2)];
   dm.csr_ent = reinterpret_cast<const int*>(base + o_ent);
+  dm.nasa = nasa ? 1 : 0;
+  dm.nasa_c = nasa ? reinterpret_cast<const double*>(base + o_nasa) : nullptr;
+  dm.eff_k = reinterpret_cast<const int*>(base + o_effk);
+  dm.eff_v = reinterpret_cast<const double*>(base + o_effv);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, h->device) == hipSuccess && prop.multiProcessorCount > 0)
     h->n_cu = prop.multiProcessorCount;

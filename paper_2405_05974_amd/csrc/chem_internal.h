@@ -21,15 +21,21 @@ constexpr double kTref = 298.15;               // K, reference of the species th
 
 // One reaction of Eq. 1 with its rate-constant parameters (Eq. 2's k vector):
 // ln A, temperature exponent and activation temperature Ea/R, plus the
-// low-pressure limit of a Lindemann falloff.  sp[] holds the species of the
-// reactant slots 0..nr-1 and product slots 3..3+np-1 (-1 when unused).
+// low-pressure limit of a falloff reaction and Troe's broadening parameters.
+// sp[] holds the species of the reactant slots 0..nr-1 and product slots
+// 3..3+np-1 (-1 when unused).  eff_off/eff_n locate the reaction's collision
+// efficiencies other than 1 in DevMech::eff_k/eff_v.
 struct alignas(16) RxParams {
   double lnA, b, EaR;
   double lnA0, b0, EaR0;
-  int type;      // 0 elementary, 1 third body (+M, unit efficiencies), 2 Lindemann falloff
+  double troe[4];  // alpha, T3, T1, T2 (CHEMKIN's T***, T*, T**)
+  int type;      // 0 elementary, 1 third body (+M), 2 falloff (Lindemann, times Troe's F when ntroe > 0)
   int rev;       // 1 reversible (reverse rate from K_c), 0 irreversible
   int nr, np;
   int sp[kSlots];
+  int ntroe;     // 0, 3 or 4 Troe parameters
+  int eff_off, eff_n;
+  int pad;
 };
 
 // Device-resident mechanism tables (all pointers are device memory).
@@ -45,6 +51,10 @@ struct DevMech {
   const RxParams* rx;      // [R]
   const int* csr_off;      // [S * (nch + 1)] start of species k's entries in chunk c
   const int* csr_ent;      // entries (j << 3) | (nu_kj + 4), sorted by j per species
+  int nasa;                // 1: every species' thermo from nasa_c (NASA 7-coefficient polynomials)
+  const double* nasa_c;    // [15][S]: T_mid, then c1..c7 for T <= T_mid, then c1..c7 above
+  const int* eff_k;        // collision efficiencies other than 1: species index
+  const double* eff_v;     //   and efficiency minus 1
 };
 
 // One box of the batched entry point, in queue order.

@@ -108,14 +108,38 @@ std::string lpc_source(const HostMech& m, bool reuse) {
   o << "  typedef const __attribute__((address_space(4))) double* ch_kptr;\n";
   o << "  ch_kptr __restrict__ K = (ch_kptr)ch_K;\n  asm volatile(\"\" : \"+s\"(K));\n";
   o << "  const double T = y[CH_S];\n  const double lnT = log(T);\n  const double invT = 1.0 / T;\n";
-  // divisions by constants are multiplications by their exact reciprocals;
-  // enthalpy and heat capacity are re-evaluated where they are used
-  // so that only the Jacobian keeps them across the reactions
+  // Divisions by constants are multiplications by their exact reciprocals;
+  // enthalpy and heat capacity are re-evaluated where they are used so that
+  // only the Jacobian keeps them across the reactions.  For a species with
+  // NASA 7-coefficient thermo each coefficient is selected by the range flag
+  // lo<k> (T <= T_mid), and the divisions of the H and S polynomials are
+  // folded into the constants.
+  auto isN = [&](int k) { return !m.nasa[k].empty(); };
+  auto nc = [&](int k, int i, double scale) {   // coefficient c_(i+1) of species k times scale
+    return "(lo" + std::to_string(k) + " ? " + kc(m.nasa[k][1 + i] * scale) + " : " +
+           kc(m.nasa[k][8 + i] * scale) + ")";
+  };
   auto Hk = [&](int k) {
+    if (isN(k))
+      return "(CH_RU * (T * (" + nc(k, 0, 1.0) + " + T * (" + nc(k, 1, 0.5) + " + T * (" + nc(k, 2, 1.0 / 3.0) +
+             " + T * (" + nc(k, 3, 0.25) + " + T * " + nc(k, 4, 0.2) + ")))) + " + nc(k, 5, 1.0) + "))";
     return "(" + kc(m.hf[k]) + " + CH_RU * (" + kc(m.a0[k]) + " * (T - CH_TREF) + " + kc(m.a1[k]) +
            " * (T * T - CH_TREF * CH_TREF) * 0.5))";
   };
-  auto Cpk = [&](int k) { return "(CH_RU * (" + kc(m.a0[k]) + " + " + kc(m.a1[k]) + " * T))"; };
+  auto Cpk = [&](int k) {
+    if (isN(k))
+      return "(CH_RU * (" + nc(k, 0, 1.0) + " + T * (" + nc(k, 1, 1.0) + " + T * (" + nc(k, 2, 1.0) + " + T * (" +
+             nc(k, 3, 1.0) + " + T * " + nc(k, 4, 1.0) + ")))))";
+    return "(CH_RU * (" + kc(m.a0[k]) + " + " + kc(m.a1[k]) + " * T))";
+  };
+  auto dCpk = [&](int k) {
+    if (isN(k))
+      return "(CH_RU * (" + nc(k, 1, 1.0) + " + T * (" + nc(k, 2, 2.0) + " + T * (" + nc(k, 3, 3.0) + " + T * " +
+             nc(k, 4, 4.0) + "))))";
+    return "CH_RU * " + kc(m.a1[k]);
+  };
+  for (int k = 0; k < S; ++k)
+    if (isN(k)) o << "  const bool lo" << k << " = T <= " << kc(m.nasa[k][0]) << ";\n";
   o << "  double sumYW = 0.0;\n";
   for (int k = 0; k < S; ++k) o << "  sumYW += y[" << k << "] * " << kc(1.0 / m.W[k]) << ";\n";
   o << "  const double Wbar = 1.0 / sumYW;\n";
@@ -132,7 +156,11 @@ std::string lpc_source(const HostMech& m, bool reuse) {
   for (int k = 0; k < S; ++k) o << "    H[" << k << "] = " << Hk(k) << ";\n";
   o << "  }\n";
   for (int k = 0; k < S; ++k) {
-    if (needG[k])
+    if (needG[k] && isN(k))
+      o << "  G[" << k << "] = (" << Hk(k) << " - T * (CH_RU * (" << nc(k, 0, 1.0) << " * lnT + T * ("
+        << nc(k, 1, 1.0) << " + T * (" << nc(k, 2, 0.5) << " + T * (" << nc(k, 3, 1.0 / 3.0) << " + T * "
+        << nc(k, 4, 0.25) << "))) + " << nc(k, 6, 1.0) << "))) * invRT;\n";
+    else if (needG[k])
       o << "  G[" << k << "] = (" << Hk(k) << " - T * (" << kc(m.s0[k]) << " + CH_RU * (" << kc(m.a0[k])
         << " * lnTr + " << kc(m.a1[k]) << " * (T - CH_TREF)))) * invRT;\n";
     else
@@ -158,15 +186,52 @@ std::string lpc_source(const HostMech& m, bool reuse) {
     o << "    double kf = kinf;\n";
     o << "    double dlnkf = (" << kc(x.b) << " + " << kc(x.Ea * kcal_to_K) << " * invT) * invT;\n";
     o << "    double dkfdM = 0.0;\n    (void)dlnkf; (void)dkfdM;\n";
+    // third-body concentration with this reaction's collision efficiencies
+    if (x.type != 0) {
+      o << "    const double Mj = Mc";
+      for (size_t i = 0; i < x.eff_k.size(); ++i)
+        o << " + " << kc(x.eff_v[i] - 1.0) << " * " << C(x.eff_k[i]);
+      o << ";\n";
+    }
     if (x.type == 2) {
       o << "    const double k0 = ch_exp(" << kc(std::log(x.A0)) << " + " << kc(x.b0) << " * lnT - "
         << kc(x.Ea0 * kcal_to_K) << " * invT);\n";
       o << "    const double dlnk0 = (" << kc(x.b0) << " + " << kc(x.Ea0 * kcal_to_K) << " * invT) * invT;\n";
-      o << "    const double Pr = k0 * Mc / kinf;\n";
+      o << "    const double Pr = k0 * Mj / kinf;\n";
+      o << "    const double dlnPr = dlnk0 - dlnkf;\n";
       o << "    kf = kinf * Pr / (1.0 + Pr);\n";
-      o << "    dlnkf = dlnkf + (dlnk0 - dlnkf) / (1.0 + Pr);\n";
+      o << "    dlnkf = dlnkf + dlnPr / (1.0 + Pr);\n";
       o << "    dkfdM = k0 / ((1.0 + Pr) * (1.0 + Pr));\n";
-      o << "    (void)dlnk0;\n";
+      o << "    (void)dlnPr;\n";
+      if (x.ntroe) {
+        // Troe's broadening factor (CHEMKIN form, logarithms base 10; log Pr at max(Pr, 1e-300))
+        const double a = x.troe[0];
+        o << "    {\n      const double e3 = ch_exp(-T * " << kc(1.0 / x.troe[1]) << "), e1 = ch_exp(-T * "
+          << kc(1.0 / x.troe[2]) << ");\n";
+        o << "      double Fc = " << kc(1.0 - a) << " * e3 + " << kc(a) << " * e1;\n";
+        o << "      double dFc = -" << kc((1.0 - a) / x.troe[1]) << " * e3 - " << kc(a / x.troe[2]) << " * e1;\n";
+        if (x.ntroe == 4) {
+          o << "      const double e2 = ch_exp(-" << kc(x.troe[3]) << " * invT);\n";
+          o << "      Fc += e2;\n      dFc += " << kc(x.troe[3]) << " * invT * invT * e2;\n";
+        }
+        o << "      const double Lc = log(Fc) * CH_INV_LN10;\n";
+        o << "      const bool live = Pr > 1e-300;\n";
+        o << "      const double lp = log(live ? Pr : 1e-300) * CH_INV_LN10;\n";
+        o << "      const double cc = -0.4 - 0.67 * Lc, nn = 0.75 - 1.27 * Lc;\n";
+        o << "      const double u = lp + cc, v = nn - 0.14 * u;\n";
+        o << "      const double f1 = u / v;\n      const double dn = 1.0 + f1 * f1;\n";
+        o << "      const double F = ch_exp(CH_LN10 * (Lc / dn));\n";
+        o << "      if (JAC) {\n";
+        o << "        const double iv2 = 1.0 / (v * v);\n";
+        o << "        const double dlogF_dlp = live ? -Lc * 2.0 * f1 * (nn * iv2) / (dn * dn) : 0.0;\n";
+        o << "        const double df1_dLc = (-0.67 * v - u * (-1.27 + 0.67 * 0.14)) * iv2;\n";
+        o << "        const double dlogF_dLc = 1.0 / dn - Lc * 2.0 * f1 * df1_dLc / (dn * dn);\n";
+        o << "        const double dLc_dT = dFc / Fc * CH_INV_LN10;\n";
+        o << "        const double dlp_dT = live ? dlnPr * CH_INV_LN10 : 0.0;\n";
+        o << "        dkfdM = F * dkfdM + F * k0 / (1.0 + Pr) * dlogF_dlp;\n";
+        o << "        dlnkf += CH_LN10 * (dlogF_dlp * dlp_dT + dlogF_dLc * dLc_dT);\n      }\n";
+        o << "      kf *= F;\n    }\n";
+      }
     }
     o << "    const double pf = " << product(x.reac, -1) << ";\n";
     o << "    const double pr = " << product(x.prod, -1) << ";\n";
@@ -192,7 +257,7 @@ std::string lpc_source(const HostMech& m, bool reuse) {
       o << "      dkr = kr * (dlnkf - dlnKc);\n";
       o << "      dkrdM = dkfdM * ratio;\n    }\n";
     }
-    o << "    const double mf = " << (x.type == 1 ? "Mc" : "1.0") << ";\n";
+    o << "    const double mf = " << (x.type == 1 ? "Mj" : "1.0") << ";\n";
     o << "    const double net = kf * pf - kr * pr;\n";
     o << "    const double Q = mf * net;\n";
     for (int k = 0; k < S; ++k)
@@ -205,6 +270,13 @@ std::string lpc_source(const HostMech& m, bool reuse) {
       o << "      const double q0 = " << (x.type == 1 ? "net" : "dkfdM * pf - dkrdM * pr") << ";\n";
       for (int k = 0; k < S; ++k)
         if (nu[k]) emit_nu_update(o, "  ak", k, nu[k], "q0");
+      // efficiencies other than 1: d[M]_j/dC_c = 1 + (eps_c - 1), the 1 being the rank-one part in ak
+      for (size_t i = 0; i < x.eff_k.size(); ++i) {
+        o << "      {\n        const double dq = q0 * " << kc(x.eff_v[i] - 1.0) << ";\n";
+        for (int k = 0; k < S; ++k)
+          if (nu[k]) emit_nu_update(o, ("    J[" + std::to_string(k) + "]").c_str(), x.eff_k[i], nu[k], "dq");
+        o << "      }\n";
+      }
     }
     for (size_t s = 0; s < x.reac.size(); ++s) {
       o << "      {\n        const double dq = mf * kf * " << product(x.reac, (int)s) << ";\n";
@@ -245,7 +317,7 @@ std::string lpc_source(const HostMech& m, bool reuse) {
   o << "      double HAC = 0.0, HdwdT = 0.0, Cpw = 0.0, Ca1 = 0.0;\n";
   o << "#pragma unroll\n      for (int k = 0; k < CH_S; ++k) {\n        HAC += H[k] * AC[k];\n"
        "        HdwdT += H[k] * dwdT[k];\n        Cpw += Cp[k] * wd[k];\n      }\n";
-  for (int k = 0; k < S; ++k) o << "      Ca1 += C[" << k << "] * CH_RU * " << kc(m.a1[k]) << ";\n";
+  for (int k = 0; k < S; ++k) o << "      Ca1 += C[" << k << "] * " << dCpk(k) << ";\n";
   o << "#pragma unroll\n      for (int c = 0; c < CH_S; ++c) {\n        double colsum = 0.0;\n"
        "#pragma unroll\n        for (int k = 0; k < CH_S; ++k) colsum += H[k] * (J[k][c] + ak[k]);\n"
        "        const double dN = (rho * iW[c]) * colsum - (Wbar * iW[c]) * HAC;\n"
@@ -268,6 +340,7 @@ std::string lpc_source(const HostMech& m, bool reuse) {
   head << "#define CH_REUSE " << (reuse ? 1 : 0) << "\n";
   head << "#define CH_RU " << lit(kRu) << "\n#define CH_RU_CGS " << lit(kRuCgs) << "\n#define CH_PATM "
        << lit(kPatm) << "\n#define CH_TREF " << lit(kTref) << "\n";
+  head << "#define CH_LN10 " << lit(std::log(10.0)) << "\n#define CH_INV_LN10 " << lit(1.0 / std::log(10.0)) << "\n";
   head << "__constant__ double ch_K[" << std::max<size_t>(pool.size(), 1) << "] = {";
   for (size_t i = 0; i < pool.size(); ++i) head << (i ? ", " : "") << lit(pool[i]);
   if (pool.empty()) head << "0.0";

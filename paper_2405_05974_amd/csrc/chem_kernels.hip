@@ -241,6 +241,47 @@ size_t integrate_lds_bytes(int np_width, int N, bool f32) {
 
 namespace {
 
+// Troe's broadening factor of a falloff reaction (CHEMKIN form, logarithms
+// base 10): F_cent = (1-a) e^(-T/T3) + a e^(-T/T1) [+ e^(-T2/T)],
+// c = -0.4 - 0.67 log F_cent, n = 0.75 - 1.27 log F_cent, d = 0.14,
+// f1 = (log Pr + c)/(n - d (log Pr + c)), log F = log F_cent / (1 + f1^2);
+// log Pr is taken at max(Pr, 1e-300).  With JAC also d ln F/dT at fixed [M]
+// (dlnPr = d ln Pr/dT) and d log F / d log Pr (0 where Pr <= 1e-300).
+template <bool JAC>
+__device__ __forceinline__ void troe_broadening(const RxParams& x, const double T, const double Pr,
+                                                const double dlnPr, double& F, double& dlnF, double& dlogF_dlp) {
+  const double a = x.troe[0], T3 = x.troe[1], T1 = x.troe[2];
+  const double e3 = exp(-T / T3), e1 = exp(-T / T1);
+  double Fc = (1.0 - a) * e3 + a * e1;
+  double dFc = -(1.0 - a) / T3 * e3 - a / T1 * e1;
+  if (x.ntroe == 4) {
+    const double e2 = exp(-x.troe[3] / T);
+    Fc += e2;
+    dFc += x.troe[3] / (T * T) * e2;
+  }
+  const double kLn10 = 2.302585092994045684;
+  const double Lc = log10(Fc);
+  const bool live = Pr > 1e-300;
+  const double lp = log10(live ? Pr : 1e-300);
+  const double cc = -0.4 - 0.67 * Lc, nn = 0.75 - 1.27 * Lc;
+  const double u = lp + cc, v = nn - 0.14 * u;
+  const double f1 = u / v;
+  const double den = 1.0 + f1 * f1;
+  F = exp(kLn10 * (Lc / den));
+  if (JAC) {
+    const double df1_dlp = nn / (v * v);
+    const double df1_dLc = (-0.67 * v - u * (-1.27 + 0.67 * 0.14)) / (v * v);
+    dlogF_dlp = live ? -Lc * 2.0 * f1 * df1_dlp / (den * den) : 0.0;
+    const double dlogF_dLc = 1.0 / den - Lc * 2.0 * f1 * df1_dLc / (den * den);
+    const double dLc_dT = dFc / (Fc * kLn10);
+    const double dlp_dT = live ? dlnPr / kLn10 : 0.0;
+    dlnF = kLn10 * (dlogF_dlp * dlp_dT + dlogF_dLc * dLc_dT);
+  } else {
+    dlnF = 0.0;
+    dlogF_dlp = 0.0;
+  }
+}
+
 // Right-hand side of the constant-pressure adiabatic reactor for the group's
 // cell at state component yr; with JAC also J = df/dy, left in the group's
 // LDS rows (row r = lane r's row; padding rows zero).
@@ -249,7 +290,8 @@ namespace {
 //   dY_k/dt = W_k wdot_k / rho,  dT/dt = -sum H_k wdot_k / sum C_k Cp_k
 // The Jacobian (Eq. 7 in the state (Y, T)) is assembled from the sparse
 // concentration-space part A = dwdot/dC (slot products, scattered in LDS), the
-// rank-1 part of [M] (unit efficiencies), the closed-form T derivatives, and
+// rank-1 part of [M] (its unit part; efficiencies other than 1 are scattered
+// as sparse corrections), the closed-form T derivatives, and
 // the chain rule through C_k(Y, T) and rho(Y, T).
 template <int NP, bool JAC>
 __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const double p, const int fixedT,
@@ -273,11 +315,24 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
   const double rho = (p * 10.0) * Wbar / (kRuCgs * T);
   const double C = isSp ? rho * Yr / W : 0.0;
   const double Mconc = gsum<NP>(C);
-  double H = 0.0, Cp = 0.0, Gd = 0.0;
+  double H = 0.0, Cp = 0.0, Gd = 0.0, dCp = 0.0;
   if (isSp) {
-    H = hf + kRu * (a0 * (T - kTref) + a1 * (T * T - kTref * kTref) * 0.5);
-    const double Sm = s0 + kRu * (a0 * log(T / kTref) + a1 * (T - kTref));
-    Cp = kRu * (a0 + a1 * T);
+    double Sm;
+    if (m.nasa) {
+      // NASA 7-coefficient polynomials of the range holding T (T <= T_mid: low)
+      const double* c = m.nasa_c + (T <= m.nasa_c[r] ? 1 : 8) * S + r;
+      const double c1 = c[0], c2 = c[S], c3 = c[2 * S], c4 = c[3 * S], c5 = c[4 * S], c6 = c[5 * S],
+                   c7 = c[6 * S];
+      Cp = kRu * (c1 + T * (c2 + T * (c3 + T * (c4 + T * c5))));
+      H = kRu * (T * (c1 + T * (c2 * 0.5 + T * (c3 * (1.0 / 3.0) + T * (c4 * 0.25 + T * (c5 * 0.2))))) + c6);
+      Sm = kRu * (c1 * lnT + T * (c2 + T * (c3 * 0.5 + T * (c4 * (1.0 / 3.0) + T * (c5 * 0.25)))) + c7);
+      dCp = kRu * (c2 + T * (2.0 * c3 + T * (3.0 * c4 + T * (4.0 * c5))));
+    } else {
+      H = hf + kRu * (a0 * (T - kTref) + a1 * (T * T - kTref * kTref) * 0.5);
+      Sm = s0 + kRu * (a0 * log(T / kTref) + a1 * (T - kTref));
+      Cp = kRu * (a0 + a1 * T);
+      dCp = kRu * a1;
+    }
     Gd = (H - T * Sm) / (kRu * T);
   }
   sh.C[lane] = C;
@@ -302,16 +357,29 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
     if (j < m.R) {
       const RxParams& x = m.rx[j];
       const int type = x.type, nr = x.nr, np = x.np;
+      // third-body concentration with this reaction's efficiencies
+      double Mj = Mconc;
+      for (int i = 0; i < x.eff_n; ++i) Mj += m.eff_v[x.eff_off + i] * sh.C[base + m.eff_k[x.eff_off + i]];
       const double kinf = exp(x.lnA + x.b * lnT - x.EaR * invT);
       double dlnkf = (x.b + x.EaR * invT) * invT;
       double kf = kinf, dkfdM = 0.0;
       if (type == 2) {
         const double k0 = exp(x.lnA0 + x.b0 * lnT - x.EaR0 * invT);
         const double dlnk0 = (x.b0 + x.EaR0 * invT) * invT;
-        const double Pr = k0 * Mconc / kinf;
+        const double Pr = k0 * Mj / kinf;
+        const double dlnPr = dlnk0 - dlnkf;
         kf = kinf * Pr / (1.0 + Pr);
-        dlnkf = dlnkf + (dlnk0 - dlnkf) / (1.0 + Pr);
+        dlnkf = dlnkf + dlnPr / (1.0 + Pr);
         dkfdM = k0 / ((1.0 + Pr) * (1.0 + Pr));
+        if (x.ntroe) {
+          double F, dlnF, dlogF_dlp;
+          troe_broadening<JAC>(x, T, Pr, dlnPr, F, dlnF, dlogF_dlp);
+          if (JAC) {
+            dkfdM = F * dkfdM + F * k0 / (1.0 + Pr) * dlogF_dlp;
+            dlnkf += dlnF;
+          }
+          kf *= F;
+        }
       }
       int sp[kSlots];
 #pragma unroll
@@ -349,7 +417,7 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
           dkrdM = dkfdM * ratio;
         }
       }
-      const double mf = (type == 1) ? Mconc : 1.0;
+      const double mf = (type == 1) ? Mj : 1.0;
       const double net = kf * pf - kr * pr;
       Q = mf * net;
       if (JAC) {
@@ -402,6 +470,11 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
               __hip_atomic_fetch_add(&Jg[r * sh.ldj + c], nu * rq[(3 + s) * kWave + src], __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_WAVEFRONT);
           }
+          // efficiencies other than 1: d[M]_j/dC_c = 1 + (eps_jc - 1), the 1 being the rank-one part in ak
+          const int eo = m.rx[jj].eff_off, en = m.rx[jj].eff_n;
+          for (int i = 0; i < en; ++i)
+            __hip_atomic_fetch_add(&Jg[r * sh.ldj + m.eff_k[eo + i]], nu * rq[2 * kWave + src] * m.eff_v[eo + i],
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         }
       }
     }
@@ -426,7 +499,7 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
     const double HAC = gsum<NP>(isSp ? H * AC : 0.0);
     const double HdwdT = gsum<NP>(isSp ? H * dwdT : 0.0);
     const double Cpw = gsum<NP>(isSp ? Cp * wd : 0.0);
-    const double Ca1 = gsum<NP>(isSp ? C * kRu * a1 : 0.0);
+    const double Ca1 = gsum<NP>(isSp ? C * dCp : 0.0);
     // column sums sum_k H_k A_kj for column j = r (LDS column read)
     double colsum = HA;
     if (isSp)
