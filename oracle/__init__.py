@@ -84,6 +84,10 @@ def _load(path: Optional[str] = None):
     lib.orc_integrate.restype = C.c_int64
     lib.orc_integrate.argtypes = [C.c_void_p, C.c_int64, dp, dp, C.c_double, C.c_double, C.c_double,
                                   C.c_double, C.POINTER(OrcOpts), C.POINTER(OrcCellStats), C.c_int]
+    lib.orc_qss_info.restype = C.c_int
+    lib.orc_qss_info.argtypes = [C.c_void_p, ip, ip]
+    lib.orc_qss_rates.restype = C.c_int
+    lib.orc_qss_rates.argtypes = [C.c_void_p, C.c_double, dp, C.c_double, dp, dp]
     lib.orc_max_threads.restype = C.c_int
     if path is None:
         _lib = lib
@@ -111,7 +115,12 @@ class Mech:
         S, R, E = C.c_int(), C.c_int(), C.c_int()
         self.lib.orc_info(h, C.byref(S), C.byref(R), C.byref(E))
         self.S, self.R, self.E = S.value, R.value, E.value
-        self.N = self.S + 1
+        # quasi-steady-state species: the state holds the ST transported ones
+        nq = C.c_int()
+        qsp = np.zeros(max(self.S, 1), dtype=np.int32)
+        self.ST = int(self.lib.orc_qss_info(h, C.byref(nq), _ip(qsp)))
+        self.qss = [int(k) for k in qsp[:nq.value]]
+        self.N = self.ST + 1
 
     def __del__(self):
         try:
@@ -143,6 +152,14 @@ class Mech:
         wdot = np.zeros(self.S)
         self.lib.orc_rates(self.h, float(T), _dp(Y), float(p), _dp(kf), _dp(kr), _dp(Q), _dp(wdot))
         return kf, kr, Q, wdot
+
+    def qss_rates(self, T: float, Y: np.ndarray, p: float):
+        """QSS concentrations (mol/cm^3) and transported production rates
+        (mol/cm^3/s) at a state of the transported species."""
+        Y = np.ascontiguousarray(Y, dtype=np.float64)
+        Cq, wd = np.zeros(max(len(self.qss), 1)), np.zeros(self.ST)
+        bad = self.lib.orc_qss_rates(self.h, float(T), _dp(Y), float(p), _dp(Cq), _dp(wd))
+        return Cq[:len(self.qss)], wd, bool(bad)
 
     def rhs(self, y: np.ndarray, p: float, fixed_T: bool = False) -> np.ndarray:
         y = np.ascontiguousarray(y, dtype=np.float64)
@@ -181,7 +198,7 @@ class Mech:
         (one record per cell) or None.  Inputs are not modified."""
         T = np.array(T, dtype=np.float64, copy=True).ravel()
         n = T.shape[0]
-        Y = np.array(Y, dtype=np.float64, copy=True).reshape(self.S, n)
+        Y = np.array(Y, dtype=np.float64, copy=True).reshape(self.ST, n)
         Y = np.ascontiguousarray(Y)
         o = OrcOpts(int(max_steps), int(q_max), int(fixed_T), int(fixed_step_n), int(jac_mode), int(jac_reuse))
         st = (OrcCellStats * n)() if want_stats else None

@@ -67,6 +67,7 @@ typedef struct {
   int neff;                  /* collision efficiencies other than 1 in [M] */
   int effk[ORC_MAX_EFF];
   double effv[ORC_MAX_EFF];
+  int drop_f, drop_r;        /* direction removed by the one-sided linearisation of QSS couplings */
 } orc_reaction;
 
 typedef struct {
@@ -79,6 +80,12 @@ typedef struct {
   double *nasa_c;            /* [S][15]: T_mid, 7 coefficients for T <= T_mid, 7 for T > T_mid */
   orc_reaction *rx;
   int *nu;                   /* [S][R] net stoichiometric coefficient nu'' - nu' */
+  /* quasi-steady-state species (Sec. 2.1): nq of them, algebraic; the state
+   * holds the ST = S - nq transported species */
+  int nq, ST;
+  int *isq;                  /* [S] position among the QSS species, or -1 */
+  int *tsp;                  /* [ST] species of state component i */
+  int *qsp;                  /* [nq] species of QSS unknown q */
 } orc_mech;
 
 /* --------------------------------------------------------------- parsing -- */
@@ -134,7 +141,8 @@ static int orc_opt_word(orc_lex *L, const char *w) {
 void orc_free(orc_mech *m) {
   if (!m) return;
   free(m->atoms); free(m->inert); free(m->W); free(m->a0); free(m->a1);
-  free(m->hf); free(m->s0); free(m->nasa); free(m->nasa_c); free(m->rx); free(m->nu); free(m);
+  free(m->hf); free(m->s0); free(m->nasa); free(m->nasa_c); free(m->rx); free(m->nu);
+  free(m->isq); free(m->tsp); free(m->qsp); free(m);
 }
 
 /* Parse the mechanism text (format documented with the generator) and derive
@@ -220,9 +228,59 @@ orc_mech *orc_load(const char *text, char *err, int errlen) {
       if (bal != 0) FAIL("reaction not atom balanced");
     }
   }
+  /* optional QSS record: the species the quasi-steady-state approximation
+   * (Eq. 4) turns into algebraic unknowns */
+  m->isq = malloc(sizeof(int) * S);
+  for (int k = 0; k < S; ++k) m->isq[k] = -1;
+  if (orc_opt_word(&L, "QSS")) {
+    if (!orc_int(&L, &m->nq) || m->nq < 0 || m->nq >= S) FAIL("bad QSS record");
+    m->qsp = malloc(sizeof(int) * (m->nq > 0 ? m->nq : 1));
+    for (int q = 0; q < m->nq; ++q) {
+      int k;
+      if (!orc_int(&L, &k) || k < 0 || k >= S || m->isq[k] >= 0 || m->inert[k]) FAIL("bad QSS species");
+      m->qsp[q] = k;
+      m->isq[k] = q;
+    }
+  } else {
+    m->qsp = malloc(sizeof(int));
+  }
+  m->ST = S - m->nq;
+  m->tsp = malloc(sizeof(int) * m->ST);
+  for (int k = 0, i = 0; k < S; ++k)
+    if (m->isq[k] < 0) m->tsp[i++] = k;
+  /* one-sided linearisation (Sec. 2.2): a direction with two or more QSS
+   * species among its reactants would make the closure nonlinear and is
+   * removed; the other direction of the reaction stays */
+  for (int j = 0; j < R; ++j) {
+    orc_reaction *x = &m->rx[j];
+    int nqr = 0, nqp = 0;
+    for (int i = 0; i < x->nr; ++i) nqr += m->isq[x->r[i]] >= 0;
+    for (int i = 0; i < x->np; ++i) nqp += m->isq[x->p[i]] >= 0;
+    x->drop_f = nqr >= 2;
+    x->drop_r = nqp >= 2;
+  }
+  /* every QSS species must be consumed by a kept direction, or its closure
+   * equation has no diagonal term */
+  for (int q = 0; q < m->nq; ++q) {
+    int k = m->qsp[q], consumed = 0;
+    for (int j = 0; j < R; ++j) {
+      const orc_reaction *x = &m->rx[j];
+      int n = m->nu[k * R + j], inr = 0, inp = 0;
+      for (int i = 0; i < x->nr; ++i) inr |= x->r[i] == k;
+      for (int i = 0; i < x->np; ++i) inp |= x->p[i] == k;
+      if ((n < 0 && inr && !x->drop_f) || (n > 0 && inp && x->rev && !x->drop_r)) consumed = 1;
+    }
+    if (!consumed) FAIL("a QSS species is never consumed");
+  }
   if (!orc_word(&L, "END")) FAIL("missing END");
 #undef FAIL
   return m;
+}
+
+int orc_qss_info(const orc_mech *m, int *nq, int *qsp) {
+  *nq = m->nq;
+  if (qsp) for (int q = 0; q < m->nq; ++q) qsp[q] = m->qsp[q];
+  return m->ST;
 }
 
 int orc_info(const orc_mech *m, int *S, int *R, int *E) {
@@ -289,12 +347,15 @@ void orc_dcp_dT(const orc_mech *m, double T, double *dCp) {
 static double orc_third_body(const orc_mech *m, int j, const double *C, double Mconc) {
   const orc_reaction *x = &m->rx[j];
   double M = Mconc;
-  for (int i = 0; i < x->neff; ++i) M += (x->effv[i] - 1.0) * C[x->effk[i]];
+  for (int i = 0; i < x->neff; ++i)
+    if (m->isq[x->effk[i]] < 0) M += (x->effv[i] - 1.0) * C[x->effk[i]];
   return M;
 }
 
-/* d[M]_j / dC_c. */
-static double orc_efficiency(const orc_reaction *x, int c) {
+/* d[M]_j / dC_c.  QSS species are not colliders: [M] sums the transported
+ * species only. */
+static double orc_efficiency(const orc_mech *m, const orc_reaction *x, int c) {
+  if (m->isq[c] >= 0) return 0.0;
   for (int i = 0; i < x->neff; ++i)
     if (x->effk[i] == c) return x->effv[i];
   return 1.0;
@@ -427,8 +488,12 @@ int orc_rates(const orc_mech *m, double T, const double *Y, double p, double *kf
 
 /* ------------------------------------------------------------- ODE system -- */
 
+static int orc_rhs_qss(const orc_mech *m, const double *y, double p, int fixed_T, double *f);
+static int orc_jac_qss(const orc_mech *m, const double *y, double p, int fixed_T, double *J);
+
 /* Right-hand side of the constant-pressure adiabatic reactor, y = (Y, T). */
 int orc_rhs(const orc_mech *m, const double *y, double p, int fixed_T, double *f) {
+  if (m->nq) return orc_rhs_qss(m, y, p, fixed_T, f);
   int S = m->S;
   double T = y[S];
   double *C = malloc(sizeof(double) * S * 4);
@@ -453,6 +518,7 @@ int orc_rhs(const orc_mech *m, const double *y, double p, int fixed_T, double *f
  * b = d wdot/dT at fixed C are accumulated reaction by reaction, then the chain
  * rule through C_k(Y, T) and rho(Y, T) is applied as plain dense products. */
 int orc_jac(const orc_mech *m, const double *y, double p, int fixed_T, double *J) {
+  if (m->nq) return orc_jac_qss(m, y, p, fixed_T, J);
   int S = m->S, R = m->R, N = S + 1;
   double T = y[S];
   double *C = malloc(sizeof(double) * (size_t)(8 * S + S * S + 2 * S * N + N));
@@ -496,7 +562,7 @@ int orc_jac(const orc_mech *m, const double *y, double p, int fixed_T, double *J
         dpr += t;
       }
       double dq = mfac * (K.kf * dpf - K.kr * dpr);
-      double eps = (x->type == 0) ? 0.0 : orc_efficiency(x, c);   /* d[M]_j/dC_c */
+      double eps = (x->type == 0) ? 0.0 : orc_efficiency(m, x, c);   /* d[M]_j/dC_c */
       if (x->type == 1) dq += eps * (K.kf * pf - K.kr * pr);
       if (x->type == 2) dq += eps * (K.dkf_dM * pf - K.dkr_dM * pr);
       for (int k = 0; k < S; ++k) A[k * S + c] += m->nu[k * R + j] * dq;
@@ -545,6 +611,295 @@ int orc_jac(const orc_mech *m, const double *y, double p, int fixed_T, double *J
   return 0;
 }
 
+/* ------------------------------------------------------------ QSS closure -- */
+
+int orc_lu(int n, double *a, int *piv);
+void orc_lu_solve(int n, const double *a, const int *piv, double *b);
+
+/* Mixture of the transported species only (the QSS species carry no mass in
+ * the state): W_bar, rho and their concentrations into C[species]. */
+static void orc_mixture_T(const orc_mech *m, double T, const double *y, double p, double *rho, double *Wbar,
+                          double *C) {
+  double inv = 0.0;
+  for (int i = 0; i < m->ST; ++i) inv += y[i] / m->W[m->tsp[i]];
+  double Wb = 1.0 / inv;
+  double r = (p * 10.0) * Wb / (ORC_RU * 1.0e7 * T);
+  for (int k = 0; k < m->S; ++k) C[k] = 0.0;
+  for (int i = 0; i < m->ST; ++i) C[m->tsp[i]] = r * y[i] / m->W[m->tsp[i]];
+  *rho = r;
+  *Wbar = Wb;
+}
+
+/* Concentrations of the QSS species from the algebraic closure (Eq. 4-6):
+ * with the quadratic couplings removed, every kept direction holds at most
+ * one QSS concentration as a factor, so the QSS production rates are affine,
+ *   wdot_QSS = A C_QSS - b,
+ * with A_mn = sum_j nu_mj (d'_nj q_fj - d''_nj q_bj)/C_n (n a reactant of the
+ * forward / a product of the reverse direction) and b the negated part free
+ * of QSS concentrations.  A C_QSS = b is solved as one dense system with
+ * partial pivoting: the plain definition of the result the paper reaches by
+ * solving the strongly connected groups in dependency order (App. B).
+ * C holds the transported concentrations; the QSS entries are filled in.
+ * K[j] receives the rate constants.  Returns 0, or 1 if A is singular. */
+static int orc_qss_solve(const orc_mech *m, double T, double *C, const double *G, const double *H, double Mconc,
+                         orc_k *K) {
+  const int nq = m->nq, R = m->R;
+  double *A = calloc((size_t)nq * nq + nq, sizeof(double)), *b = A + nq * nq;
+  int *piv = malloc(sizeof(int) * nq);
+  for (int j = 0; j < R; ++j) {
+    const orc_reaction *x = &m->rx[j];
+    double Mj = orc_third_body(m, j, C, Mconc);
+    K[j] = orc_rate_constants(m, j, T, G, H, Mj);
+    double mfac = (x->type == 1) ? Mj : 1.0;
+    int any = 0;
+    for (int q = 0; q < nq; ++q) any |= m->nu[m->qsp[q] * R + j] != 0;
+    if (!any) continue;
+    /* forward: k_f times the reactant concentrations, one of which may be QSS */
+    if (!x->drop_f) {
+      double c = mfac * K[j].kf;
+      int n = -1;
+      for (int i = 0; i < x->nr; ++i) {
+        if (m->isq[x->r[i]] >= 0) n = m->isq[x->r[i]];
+        else c *= C[x->r[i]];
+      }
+      for (int q = 0; q < nq; ++q) {
+        int nu = m->nu[m->qsp[q] * R + j];
+        if (!nu) continue;
+        if (n >= 0) A[q * nq + n] += nu * c;
+        else b[q] -= nu * c;
+      }
+    }
+    if (x->rev && !x->drop_r) {
+      double c = mfac * K[j].kr;
+      int n = -1;
+      for (int i = 0; i < x->np; ++i) {
+        if (m->isq[x->p[i]] >= 0) n = m->isq[x->p[i]];
+        else c *= C[x->p[i]];
+      }
+      for (int q = 0; q < nq; ++q) {
+        int nu = m->nu[m->qsp[q] * R + j];
+        if (!nu) continue;
+        if (n >= 0) A[q * nq + n] -= nu * c;
+        else b[q] += nu * c;
+      }
+    }
+  }
+  int info = orc_lu(nq, A, piv);
+  if (!info) orc_lu_solve(nq, A, piv, b);
+  for (int q = 0; q < nq; ++q) C[m->qsp[q]] = info ? NAN : b[q];
+  free(A);
+  free(piv);
+  return info != 0;
+}
+
+/* Net production rates of every species at concentrations C (QSS ones
+ * included) with the linearised directions removed. */
+static void orc_qss_wdot(const orc_mech *m, const double *C, double Mconc, const orc_k *K, double *wdot) {
+  const int S = m->S, R = m->R;
+  for (int k = 0; k < S; ++k) wdot[k] = 0.0;
+  for (int j = 0; j < R; ++j) {
+    const orc_reaction *x = &m->rx[j];
+    double Mj = orc_third_body(m, j, C, Mconc);
+    double qf = 0.0, qr = 0.0;
+    if (!x->drop_f) {
+      qf = K[j].kf;
+      for (int i = 0; i < x->nr; ++i) qf *= C[x->r[i]];
+    }
+    if (x->rev && !x->drop_r) {
+      qr = K[j].kr;
+      for (int i = 0; i < x->np; ++i) qr *= C[x->p[i]];
+    }
+    double q = qf - qr;
+    if (x->type == 1) q *= Mj;
+    for (int k = 0; k < S; ++k) wdot[k] += m->nu[k * R + j] * q;
+  }
+}
+
+/* QSS concentrations (mol/cm^3) and the production rates of the transported
+ * species at a state (T, Y of the transported species), for tests. */
+int orc_qss_rates(const orc_mech *m, double T, const double *Y, double p, double *Cq, double *wdot_T) {
+  const int S = m->S;
+  double *C = malloc(sizeof(double) * 5 * S), *H = C + S, *G = H + S, *Sm = G + S, *wd = Sm + S;
+  orc_k *K = malloc(sizeof(orc_k) * (m->R > 0 ? m->R : 1));
+  double rho, Wbar;
+  orc_mixture_T(m, T, Y, p, &rho, &Wbar, C);
+  orc_thermo(m, T, H, Sm, NULL, G);
+  for (int k = 0; k < S; ++k) G[k] /= ORC_RU * T;
+  double Mconc = 0.0;
+  for (int i = 0; i < m->ST; ++i) Mconc += C[m->tsp[i]];
+  int bad = orc_qss_solve(m, T, C, G, H, Mconc, K);
+  orc_qss_wdot(m, C, Mconc, K, wd);
+  if (Cq) for (int q = 0; q < m->nq; ++q) Cq[q] = C[m->qsp[q]];
+  if (wdot_T) for (int i = 0; i < m->ST; ++i) wdot_T[i] = wd[m->tsp[i]];
+  free(C);
+  free(K);
+  return bad;
+}
+
+/* Reduced right-hand side, y = (Y of the transported species, T). */
+static int orc_rhs_qss(const orc_mech *m, const double *y, double p, int fixed_T, double *f) {
+  const int S = m->S, ST = m->ST;
+  double T = y[ST];
+  double *C = malloc(sizeof(double) * 6 * S), *H = C + S, *G = H + S, *Sm = G + S, *Cp = Sm + S, *wd = Cp + S;
+  orc_k *K = malloc(sizeof(orc_k) * (m->R > 0 ? m->R : 1));
+  double rho, Wbar;
+  orc_mixture_T(m, T, y, p, &rho, &Wbar, C);
+  orc_thermo(m, T, H, Sm, Cp, G);
+  for (int k = 0; k < S; ++k) G[k] /= ORC_RU * T;
+  double Mconc = 0.0;
+  for (int i = 0; i < ST; ++i) Mconc += C[m->tsp[i]];
+  orc_qss_solve(m, T, C, G, H, Mconc, K);
+  orc_qss_wdot(m, C, Mconc, K, wd);
+  double num = 0.0, den = 0.0;
+  for (int i = 0; i < ST; ++i) {
+    int k = m->tsp[i];
+    f[i] = m->W[k] * wd[k] / rho;
+    num += H[k] * wd[k];
+    den += C[k] * Cp[k];
+  }
+  f[ST] = fixed_T ? 0.0 : -num / den;
+  free(C);
+  free(K);
+  return 0;
+}
+
+/* Jacobian of the reduced right-hand side (the paper's QSS chain rule,
+ * Sec. 3.2): the QSS concentrations depend on the transported ones and on T
+ * through the closure wdot_QSS = 0, so with the concentration-space blocks
+ * A_TT, A_TQ, A_QT, A_QQ of d wdot/dC (the linearised mechanism, at the
+ * closure's C) and the T-derivatives b_T, b_Q at fixed C,
+ *   d wdot_T/dC_T = A_TT - A_TQ A_QQ^-1 A_QT,  d wdot_T/dT = b_T - A_TQ A_QQ^-1 b_Q
+ * (A_QQ is the closure matrix).  The chain rule through C(Y, T) and rho(Y, T)
+ * of the transported mixture then follows as in orc_jac. */
+static int orc_jac_qss(const orc_mech *m, const double *y, double p, int fixed_T, double *J) {
+  const int S = m->S, R = m->R, ST = m->ST, nq = m->nq, N = ST + 1;
+  double T = y[ST];
+  double *C = malloc(sizeof(double) * (size_t)(8 * S + S * S + nq * (ST + 1) + nq * nq + 2 * ST * N + N));
+  double *H = C + S, *Cp = H + S, *G = Cp + S, *Sm = G + S, *wd = Sm + S, *b = wd + S, *dCp = b + S;
+  double *A = dCp + S;              /* [S][S] d wdot_k / dC_c over all species */
+  double *X = A + S * S;            /* [nq][ST+1]: A_QQ^-1 [A_QT | b_Q] */
+  double *Aqq = X + nq * (ST + 1);  /* [nq][nq] */
+  double *dC = Aqq + nq * nq;       /* [ST][N] */
+  double *dw = dC + ST * N;         /* [ST][N] */
+  double *drho = dw + ST * N;       /* [N] */
+  orc_k *K = malloc(sizeof(orc_k) * (R > 0 ? R : 1));
+  int *piv = malloc(sizeof(int) * (nq > 0 ? nq : 1));
+  double rho, Wbar;
+  orc_mixture_T(m, T, y, p, &rho, &Wbar, C);
+  orc_thermo(m, T, H, Sm, Cp, G);
+  orc_dcp_dT(m, T, dCp);
+  for (int k = 0; k < S; ++k) G[k] /= ORC_RU * T;
+  double Mconc = 0.0;
+  for (int i = 0; i < ST; ++i) Mconc += C[m->tsp[i]];
+  orc_qss_solve(m, T, C, G, H, Mconc, K);
+  orc_qss_wdot(m, C, Mconc, K, wd);
+  for (int i = 0; i < S * S; ++i) A[i] = 0.0;
+  for (int k = 0; k < S; ++k) b[k] = 0.0;
+  for (int j = 0; j < R; ++j) {
+    const orc_reaction *x = &m->rx[j];
+    double Mj = orc_third_body(m, j, C, Mconc);
+    double kf = x->drop_f ? 0.0 : K[j].kf, dkf = x->drop_f ? 0.0 : K[j].dkf;
+    double dkf_dM = x->drop_f ? 0.0 : K[j].dkf_dM;
+    int rev = x->rev && !x->drop_r;
+    double kr = rev ? K[j].kr : 0.0, dkr = rev ? K[j].dkr : 0.0, dkr_dM = rev ? K[j].dkr_dM : 0.0;
+    double pf = 1.0, pr = 1.0;
+    for (int i = 0; i < x->nr; ++i) pf *= C[x->r[i]];
+    for (int i = 0; i < x->np; ++i) pr *= C[x->p[i]];
+    double mfac = (x->type == 1) ? Mj : 1.0;
+    double dq_dT = mfac * (dkf * pf - dkr * pr);
+    for (int c = 0; c < S; ++c) {
+      double dpf = 0.0, dpr = 0.0;
+      for (int i = 0; i < x->nr; ++i) {
+        if (x->r[i] != c) continue;
+        double t = 1.0;
+        for (int i2 = 0; i2 < x->nr; ++i2) if (i2 != i) t *= C[x->r[i2]];
+        dpf += t;
+      }
+      for (int i = 0; i < x->np; ++i) {
+        if (x->p[i] != c) continue;
+        double t = 1.0;
+        for (int i2 = 0; i2 < x->np; ++i2) if (i2 != i) t *= C[x->p[i2]];
+        dpr += t;
+      }
+      double dq = mfac * (kf * dpf - kr * dpr);
+      double eps = (x->type == 0) ? 0.0 : orc_efficiency(m, x, c);
+      if (x->type == 1) dq += eps * (kf * pf - kr * pr);
+      if (x->type == 2) dq += eps * (dkf_dM * pf - dkr_dM * pr);
+      for (int k = 0; k < S; ++k) A[k * S + c] += m->nu[k * R + j] * dq;
+    }
+    for (int k = 0; k < S; ++k) b[k] += m->nu[k * R + j] * dq_dT;
+  }
+  /* X = A_QQ^-1 [A_QT | b_Q] */
+  for (int q = 0; q < nq; ++q) {
+    for (int q2 = 0; q2 < nq; ++q2) Aqq[q * nq + q2] = A[m->qsp[q] * S + m->qsp[q2]];
+  }
+  orc_lu(nq, Aqq, piv);
+  double *col = malloc(sizeof(double) * (nq > 0 ? nq : 1));
+  for (int c = 0; c <= ST; ++c) {
+    for (int q = 0; q < nq; ++q) col[q] = c < ST ? A[m->qsp[q] * S + m->tsp[c]] : b[m->qsp[q]];
+    orc_lu_solve(nq, Aqq, piv, col);
+    for (int q = 0; q < nq; ++q) X[q * (ST + 1) + c] = col[q];
+  }
+  free(col);
+  /* dC_m/dY_j = delta_mj rho/W_m - C_m Wbar/W_j ; dC_m/dT = -C_m/T (transported) */
+  for (int a = 0; a < ST; ++a) {
+    int ka = m->tsp[a];
+    for (int j = 0; j < ST; ++j) dC[a * N + j] = (a == j ? rho / m->W[ka] : 0.0) - C[ka] * Wbar / m->W[m->tsp[j]];
+    dC[a * N + ST] = -C[ka] / T;
+  }
+  for (int j = 0; j < ST; ++j) drho[j] = -rho * Wbar / m->W[m->tsp[j]];
+  drho[ST] = -rho / T;
+  /* reduced concentration-space Jacobian, then the chain rule */
+  for (int a = 0; a < ST; ++a) {
+    int ka = m->tsp[a];
+    for (int j = 0; j < N; ++j) {
+      double s = 0.0;
+      for (int c = 0; c < ST; ++c) {
+        double ared = A[ka * S + m->tsp[c]];
+        for (int q = 0; q < nq; ++q) ared -= A[ka * S + m->qsp[q]] * X[q * (ST + 1) + c];
+        s += ared * dC[c * N + j];
+      }
+      if (j == ST) {
+        double bred = b[ka];
+        for (int q = 0; q < nq; ++q) bred -= A[ka * S + m->qsp[q]] * X[q * (ST + 1) + ST];
+        s += bred;
+      }
+      dw[a * N + j] = s;
+    }
+  }
+  for (int a = 0; a < ST; ++a) {
+    int ka = m->tsp[a];
+    for (int j = 0; j < N; ++j)
+      J[a * N + j] = m->W[ka] / rho * dw[a * N + j] - m->W[ka] * wd[ka] / (rho * rho) * drho[j];
+  }
+  double num = 0.0, den = 0.0;
+  for (int a = 0; a < ST; ++a) {
+    int ka = m->tsp[a];
+    num += H[ka] * wd[ka];
+    den += C[ka] * Cp[ka];
+  }
+  for (int j = 0; j < N; ++j) {
+    if (fixed_T) { J[ST * N + j] = 0.0; continue; }
+    double dnum = 0.0, dden = 0.0;
+    for (int a = 0; a < ST; ++a) {
+      int ka = m->tsp[a];
+      dnum += H[ka] * dw[a * N + j];
+      dden += Cp[ka] * dC[a * N + j];
+    }
+    if (j == ST)
+      for (int a = 0; a < ST; ++a) {
+        int ka = m->tsp[a];
+        dnum += Cp[ka] * wd[ka];
+        dden += C[ka] * dCp[ka];
+      }
+    J[ST * N + j] = -dnum / den + num * dden / (den * den);
+  }
+  free(C);
+  free(K);
+  free(piv);
+  return 0;
+}
+
 /* ------------------------------------------------------------ linear algebra */
 
 /* In-place LU with partial pivoting (row swaps; the first row index wins among
@@ -588,7 +943,7 @@ double orc_enthalpy(const orc_mech *m, double T, const double *Y) {
   double h = 0.0;
   double *H = malloc(sizeof(double) * m->S);
   orc_thermo(m, T, H, NULL, NULL, NULL);
-  for (int k = 0; k < m->S; ++k) h += Y[k] * H[k] / m->W[k];
+  for (int i = 0; i < m->ST; ++i) h += Y[i] * H[m->tsp[i]] / m->W[m->tsp[i]];
   free(H);
   return h;
 }
@@ -607,7 +962,11 @@ double orc_temperature_from_h(const orc_mech *m, double h, const double *Y) {
     for (int it = 0; it < 200; ++it) {
       orc_thermo(m, T, H, NULL, Cp, NULL);
       double g = -h, dg = 0.0;
-      for (int k = 0; k < m->S; ++k) { g += Y[k] * H[k] / m->W[k]; dg += Y[k] * Cp[k] / m->W[k]; }
+      for (int i = 0; i < m->ST; ++i) {
+        int k = m->tsp[i];
+        g += Y[i] * H[k] / m->W[k];
+        dg += Y[i] * Cp[k] / m->W[k];
+      }
       if (g > 0) hi = T; else lo = T;
       double Tn = T - g / dg;
       if (!(Tn > lo && Tn < hi)) Tn = 0.5 * (lo + hi);
@@ -618,8 +977,9 @@ double orc_temperature_from_h(const orc_mech *m, double h, const double *Y) {
     return T;
   }
   double al = 0.0, be = 0.0, ga = 0.0;
-  for (int k = 0; k < m->S; ++k) {
-    double w = Y[k] / m->W[k];
+  for (int i = 0; i < m->ST; ++i) {
+    int k = m->tsp[i];
+    double w = Y[i] / m->W[k];
     al += w * (m->hf[k] - ORC_RU * m->a0[k] * ORC_TREF - ORC_RU * m->a1[k] * ORC_TREF * ORC_TREF / 2.0);
     be += w * ORC_RU * m->a0[k];
     ga += w * ORC_RU * m->a1[k] / 2.0;
@@ -743,7 +1103,7 @@ static void orc_rescale(int n, double **D, int mdim, double r) {
  * number of right-hand sides evaluated. */
 static int orc_jac_dq(const orc_mech *m, const double *y, double p, int fixed_T, const double *fy,
                       const double *w, double h, int j0, double *J, double *ytmp, double *f1) {
-  const int S = m->S, N = S + 1;
+  const int N = m->ST + 1;
   const double u = 2.220446049250313e-16;
   const double fnorm = orc_wrms(N, fy, w);
   const double minc = fnorm != 0.0 ? 1000.0 * fabs(h) * u * N * fnorm : 1.0;
@@ -760,7 +1120,7 @@ static int orc_jac_dq(const orc_mech *m, const double *y, double p, int fixed_T,
 
 /* The difference-quotient Jacobian at one state (all columns), for tests. */
 int orc_jac_fd(const orc_mech *m, const double *y, double p, int fixed_T, const double *w, double h, double *J) {
-  const int N = m->S + 1;
+  const int N = m->ST + 1;
   double *t = malloc(sizeof(double) * 3 * (size_t)N);
   orc_rhs(m, y, p, fixed_T, t);
   int nr = orc_jac_dq(m, y, p, fixed_T, t, w, h, 0, J, t + N, t + 2 * N);
@@ -770,7 +1130,7 @@ int orc_jac_fd(const orc_mech *m, const double *y, double p, int fixed_T, const 
 
 static void orc_integrate_cell(const orc_mech *m, double *y, double p, double dt, double rtol, double atol,
                                const orc_opts *o, orc_cell_stats *st) {
-  int S = m->S, N = S + 1;
+  int S = m->ST, N = S + 1;   /* state: the transported species and T */
   int q_max = o->q_max < 1 ? 1 : (o->q_max > ORC_QMAX ? ORC_QMAX : o->q_max);
   double *buf = malloc(sizeof(double) * (size_t)(N * (ORC_QMAX + 3 + 10) + N * N));
   double *D[ORC_QMAX + 3];
@@ -977,7 +1337,7 @@ out:
  * OpenMP default.  Returns the number of failed cells. */
 int64_t orc_integrate(const orc_mech *m, int64_t n, double *T, double *Y, double p, double dt, double rtol,
                       double atol, const orc_opts *o, orc_cell_stats *stats, int nthreads) {
-  int S = m->S;
+  int S = m->ST;
   int64_t failed = 0;
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);

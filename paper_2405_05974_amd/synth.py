@@ -47,6 +47,8 @@ type 0 = elementary, 1 = third body (+M), 2 = falloff (+M) whose
 low-pressure limit (A0, b0, Ea0) follows (Lindemann form, times Troe's
 broadening factor when TROE follows; T3, T1, T2 are CHEMKIN's T***, T*, T**).
 EFF lists collision efficiencies other than 1 in [M] for types 1 and 2.
+An optional record `QSS <n> <k_1> .. <k_n>` before END names the species
+treated as quasi-steady (algebraic; the state holds the others in order).
 NASA7 gives CHEMKIN's 7-coefficient polynomials in two ranges split at T_mid.  Reactant and
 product lists hold 0-based species indices, a repeated index meaning a
 stoichiometric coefficient of 2 (at most 3 entries per side).  Floats are
@@ -94,6 +96,17 @@ class Mechanism:
     reactions: List[Reaction]
     label: str = ""
     nasa: Optional[List[Optional[Tuple[float, ...]]]] = None   # per species: (T_mid, 7 low, 7 high) or None
+    qss: Optional[List[int]] = None     # quasi-steady-state species (algebraic, not in the state)
+
+    @property
+    def transported(self) -> List[int]:
+        """Species of the integrated state, in order (all but the QSS ones)."""
+        q = set(self.qss or [])
+        return [k for k in range(self.n_species) if k not in q]
+
+    @property
+    def n_state_species(self) -> int:
+        return self.n_species - len(self.qss or [])
 
     @property
     def n_species(self) -> int:
@@ -141,6 +154,8 @@ def write_mechanism(m: Mechanism) -> str:
             for k in sorted(r.eff):
                 fields += [str(int(k)), _f(r.eff[k])]
         out.append(" ".join(fields))
+    if m.qss:
+        out.append(f"QSS {len(m.qss)} " + " ".join(str(int(k)) for k in m.qss))
     out.append("END")
     return "\n".join(out) + "\n"
 
@@ -280,6 +295,73 @@ def make_real_mechanism(S: int, R: int, E: int, seed: int, troe_fraction: float 
             ks = rng.choice(S, size=min(3, S), replace=False)
             r.eff = {int(k): float(EFF_CHOICES[int(rng.integers(0, len(EFF_CHOICES)))]) for k in ks}
     m.label = f"G_real({S},{R},{E},seed {seed})"
+    return m
+
+
+# ------------------------------------------- quasi-steady-state species (f3) ----
+
+def _qss_branching(r: Reaction, qss: set) -> bool:
+    """A direction of r with exactly one QSS reactant yields two or more QSS
+    species (integer bookkeeping on the reaction lists)."""
+    sides = [(r.reactants, r.products)] + ([(r.products, r.reactants)] if r.reversible else [])
+    return any(sum(i in qss for i in rs) == 1 and sum(i in qss for i in ps) >= 2 for rs, ps in sides)
+
+
+def _qss_leaks(reactions: List[Reaction], qss: set) -> bool:
+    """Every QSS species is consumed by some direction with it as the only
+    QSS reactant and no QSS product."""
+    leak = {k: False for k in qss}
+    for r in reactions:
+        sides = [(r.reactants, r.products)] + ([(r.products, r.reactants)] if r.reversible else [])
+        for rs, ps in sides:
+            qr = [i for i in rs if i in qss]
+            if len(qr) == 1 and not any(i in qss for i in ps):
+                leak[qr[0]] = True
+    return all(leak.values())
+
+
+def make_qss_mechanism(S: int, R: int, E: int, seed: int, n_qss: int, speedup: float = 1e2,
+                       dh_f: float = 1.5e5, max_draws: int = 200) -> Mechanism:
+    """G(S,R,E,seed) with n_qss of its reactive species made quasi-steady
+    (the paper's reduced mechanisms are not available, so a selection rule on
+    the synthetic family stands in).  From a second stream seeded
+    seed + 104729: n_qss species are drawn uniformly among the reactive
+    species that take part in at least two reactions.  Reactions with a
+    direction that turns one QSS species into two are removed (kept, they
+    can make the closure singular); the draw is repeated until every QSS
+    species keeps a direction that consumes it into transported species
+    only.  With that, every column of the closure matrix is diagonally
+    dominant, so the closure is regular at every state.  Each chosen species'
+    formation enthalpy is raised by dh_f J/mol (a short-lived,
+    low-concentration intermediate), and the pre-exponential factor of every
+    reaction involving one is multiplied by `speedup` (fast).  Reactions with
+    two QSS species on one side stay: their quadratic couplings are left to
+    the one-sided linearisation."""
+    m = make_mechanism(S, R, E, seed)
+    rng = np.random.default_rng(seed + 104729)
+    count = np.zeros(S, dtype=int)
+    for r in m.reactions:
+        for k in set(r.reactants) | set(r.products):
+            count[k] += 1
+    cand = [k for k in range(S - 1) if count[k] >= 2]
+    if len(cand) < n_qss:
+        raise ValueError("not enough QSS candidates")
+    for _ in range(max_draws):
+        pick = set(int(k) for k in rng.choice(cand, size=n_qss, replace=False))
+        kept = [r for r in m.reactions if not _qss_branching(r, pick)]
+        if _qss_leaks(kept, pick):
+            break
+    else:
+        raise RuntimeError("no admissible QSS set")
+    m.reactions = kept
+    m.qss = sorted(pick)
+    m.hf = m.hf.copy()
+    for k in m.qss:
+        m.hf[k] += dh_f
+    for r in m.reactions:
+        if pick & (set(r.reactants) | set(r.products)):
+            r.A *= speedup
+    m.label = f"G_qss({S},{R},{E},seed {seed},{n_qss} QSS; {len(m.reactions)} reactions kept)"
     return m
 
 

@@ -328,6 +328,94 @@ def pin_real_complex_step(lib):
     return True
 
 
+# ---------------------------------------------- quasi-steady-state species (f3)
+
+def pin_qss_numpy(lib):
+    """The reduced rhs and its Jacobian (QSS closure, one-sided linearisation,
+    chain rule through the closure) against the numpy reduced rhs, which
+    reads the closure matrix off its own affine QSS production rates, and
+    complex-step derivatives of it; on the hand-built QSS mechanism with its
+    quadratic couplings, below and above 1000 K and at two pressures."""
+    m = mechs.qss_tiny()
+    om = oracle.Mech(m.to_text(), lib_path=lib)
+    rng = np.random.default_rng(3)
+    for T in (800.0, 1400.0, 2200.0):
+        for p in (P, 6e6):
+            Y = np.concatenate([0.3 * rng.dirichlet(np.ones(5)), [0.7]])
+            y = np.concatenate([Y, [T]])
+            f, fn = om.rhs(y, p), rhs_numpy.rhs_qss(m, y, p)
+            if np.abs(f - fn).max() > 1e-12 * np.abs(fn).max():
+                return False
+            J, Jc = om.jac(y, p), rhs_numpy.jac_complex_step(m, y, p)
+            row = np.abs(J - Jc).max(axis=1) / np.maximum(np.abs(Jc).max(axis=1), 1e-300)
+            if row.max() > 1e-11:
+                return False
+    return True
+
+
+def _qss_full_and_reduced(lib, dh):
+    m = mechs.qss_tiny(coupling=False, dh_qss=dh)
+    red = oracle.Mech(m.to_text(), lib_path=lib)
+    full_m = mechs.qss_tiny(coupling=False, dh_qss=dh)
+    full_m.qss = None
+    full = oracle.Mech(full_m.to_text(), lib_path=lib)
+    return m, red, full
+
+
+def pin_qss_validity(lib):
+    """Quasi-steady state is the limit of a fast, scarce intermediate: with
+    no quadratic coupling, the reduced integration approaches the full one
+    (X and Y integrated, started at their closure values) as X and Y are made
+    less stable, from ~1e-5 in T/T to the integration tolerance."""
+    T0 = np.array([1150.0, 1300.0])
+    Y0 = np.array([[0.1, 0.05], [0.1, 0.1], [0.05, 0.05], [0.02, 0.05], [0.03, 0.05], [0.7, 0.7]])
+    diffs = []
+    for dh in (0.0, 6e4):
+        m, red, full = _qss_full_and_reduced(lib, dh)
+        W = full.weights()
+        ts = m.transported
+        Yf = np.zeros((m.n_species, 2))
+        for i in range(2):
+            Cq, _, _ = red.qss_rates(T0[i], Y0[:, i], P)
+            rho = P * 10 / (RU * 1e7 * T0[i]) / np.sum(Y0[:, i] / W[ts])
+            Yf[ts, i] = Y0[:, i]
+            Yf[m.qss, i] = Cq * W[m.qss] / rho
+        Yf /= Yf.sum(axis=0)
+        T1, Y1, s1 = red.integrate(T0, Y0, P, 2e-4, 1e-10, 1e-16)
+        T2, Y2, s2 = full.integrate(T0, Yf, P, 2e-4, 1e-10, 1e-16)
+        if s1["status"].any() or s2["status"].any():
+            return False
+        diffs.append(max((np.abs(T1 - T2) / T2).max(), np.abs(Y1 - Y2[ts]).max()))
+    return diffs[0] > 1e-6 and diffs[1] < 1e-8 and diffs[1] < 1e-3 * diffs[0]
+
+
+def pin_qss_closure_zero(lib):
+    """At the closure's concentrations the full mechanism (regular rate
+    code, QSS species as ordinary species) produces no net X or Y, and its
+    transported production rates are the reduced ones.  The full state holds
+    every concentration of the reduced one plus the QSS ones, so its pressure
+    is raised by the QSS share of the moles (ideal gas)."""
+    m, red, full = _qss_full_and_reduced(lib, 3e4)
+    W = full.weights()
+    ts = m.transported
+    for T in (1100.0, 1700.0):
+        Y0 = np.array([0.08, 0.07, 0.06, 0.05, 0.04, 0.7])
+        Cq, wd, bad = red.qss_rates(T, Y0, P)
+        rho = P * 10 / (RU * 1e7 * T) / np.sum(Y0 / W[ts])
+        C = np.zeros(m.n_species)
+        C[ts] = rho * Y0 / W[ts]
+        C[m.qss] = Cq
+        Yf = C * W / np.sum(C * W)
+        pf = P * np.sum(C) / np.sum(C[ts])
+        kf, kr, Q, wf = full.rates(T, Yf, pf)
+        gross = np.abs(full.nu()) @ np.abs(Q)
+        if bad or np.abs(wf[m.qss]).max() > 1e-12 * gross[m.qss].max():
+            return False
+        if np.abs(wf[ts] - wd).max() > 1e-9 * gross[ts].max():
+            return False
+    return True
+
+
 MUTATIONS = [
     ("standard-state exponent sign", "pow(c0, (double)dnu)", "pow(c0, (double)-dnu)", pin_gibbs_minimum),
     ("third body drops [M]", "if (x->type == 1) q *= Mj;", "if (x->type == 9) q *= Mj;",
@@ -357,10 +445,18 @@ MUTATIONS = [
      pin_troe_complex_step),
     ("efficiency offset", "M += (x->effv[i] - 1.0) * C[x->effk[i]];", "M += x->effv[i] * C[x->effk[i]];",
      pin_efficiency_decay),
-    ("efficiency in the Jacobian", "double eps = (x->type == 0) ? 0.0 : orc_efficiency(x, c);",
+    ("efficiency in the Jacobian", "double eps = (x->type == 0) ? 0.0 : orc_efficiency(m, x, c);   /* d[M]_j/dC_c */",
      "double eps = (x->type == 0) ? 0.0 : 1.0;", pin_real_complex_step),
     ("heat-capacity slope in the T row", "dden += C[k] * dCp[k];", "dden += 0.0 * dCp[k];",
      pin_real_complex_step),
+    ("QSS closure constant term sign", "else b[q] -= nu * c;", "else b[q] += nu * c;", pin_qss_closure_zero),
+    ("QSS linearisation threshold", "x->drop_f = nqr >= 2;", "x->drop_f = nqr >= 3;", pin_qss_numpy),
+    ("QSS chain-rule sign", "ared -= A[ka * S + m->qsp[q]] * X[q * (ST + 1) + c];",
+     "ared += A[ka * S + m->qsp[q]] * X[q * (ST + 1) + c];", pin_qss_numpy),
+    ("QSS species as colliders", "if (m->isq[c] >= 0) return 0.0;", "if (m->isq[c] >= 0) return 1.0;",
+     pin_qss_numpy),
+    ("QSS reverse coefficient sign", "if (n >= 0) A[q * nq + n] -= nu * c;", "if (n >= 0) A[q * nq + n] += nu * c;",
+     pin_qss_validity),
 ]
 
 
