@@ -22,6 +22,7 @@ struct HostReaction {
   double troe[4] = {0, 0, 0, 0};
   std::vector<int> eff_k;           // collision efficiencies other than 1 in [M]
   std::vector<double> eff_v;
+  int drop_f = 0, drop_r = 0;       // direction removed by the one-sided linearisation of QSS couplings
 };
 
 struct HostMech {
@@ -32,6 +33,10 @@ struct HostMech {
   // above; empty when the species uses the linear cp form
   std::vector<std::vector<double>> nasa;
   std::vector<HostReaction> rx;
+  // quasi-steady-state species (algebraic, not in the state), in the order
+  // of the mechanism's QSS record
+  std::vector<int> qss;
+  int n_state_species() const { return (int)W.size() - (int)qss.size(); }
   bool any_nasa() const {
     for (const auto& v : nasa)
       if (!v.empty()) return true;

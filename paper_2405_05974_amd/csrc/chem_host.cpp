@@ -116,9 +116,11 @@ int parse_mechanism(const std::string& text, HostMech& m) {
   m.atoms.assign(S, std::vector<int>(E, 0));
   m.W.resize(S); m.a0.resize(S); m.a1.resize(S); m.hf.resize(S); m.s0.resize(S);
   m.nasa.assign(S, {});
+  std::vector<int> inert_of(S, 0);
   for (int k = 0; k < S; ++k) {
     int inert = 0, total = 0;
     if (!tk.skip() || !tk.integer(inert)) return fail(CHEM_ERR_PARSE, "bad species line");
+    inert_of[k] = inert;
     double w = 0.0;
     for (int e = 0; e < E; ++e) {
       if (!tk.integer(m.atoms[k][e]) || m.atoms[k][e] < 0) return fail(CHEM_ERR_PARSE, "bad atom count");
@@ -184,6 +186,39 @@ int parse_mechanism(const std::string& text, HostMech& m) {
       for (int s : x.reac) bal -= m.atoms[s][e];
       if (bal != 0) return fail(CHEM_ERR_PARSE, "reaction " + std::to_string(j) + " is not atom balanced");
     }
+  }
+  // optional QSS record: species the quasi-steady-state approximation turns
+  // into algebraic unknowns (Sec. 2.1, Eq. 4)
+  std::vector<char> isq(S, 0);
+  if (tk.opt_word("QSS")) {
+    int nq = 0;
+    if (!tk.integer(nq) || nq < 0 || nq >= S) return fail(CHEM_ERR_PARSE, "bad QSS record");
+    for (int q = 0; q < nq; ++q) {
+      int k = -1;
+      if (!tk.integer(k) || k < 0 || k >= S || isq[k] || inert_of[k])
+        return fail(CHEM_ERR_PARSE, "bad QSS species in the QSS record");
+      isq[k] = 1;
+      m.qss.push_back(k);
+    }
+  }
+  // one-sided linearisation (Sec. 2.2): a direction with two or more QSS
+  // reactants is removed, the other direction stays
+  for (HostReaction& x : m.rx) {
+    int nqr = 0, nqp = 0;
+    for (int k : x.reac) nqr += isq[k];
+    for (int k : x.prod) nqp += isq[k];
+    x.drop_f = nqr >= 2;
+    x.drop_r = nqp >= 2;
+  }
+  for (int k : m.qss) {
+    bool consumed = false;
+    for (const HostReaction& x : m.rx) {
+      int nu = 0, inr = 0, inp = 0;
+      for (int s : x.prod) { nu += (s == k); inp |= (s == k); }
+      for (int s : x.reac) { nu -= (s == k); inr |= (s == k); }
+      if ((nu < 0 && inr && !x.drop_f) || (nu > 0 && inp && x.rev && !x.drop_r)) consumed = true;
+    }
+    if (!consumed) return fail(CHEM_ERR_PARSE, "QSS species " + std::to_string(k) + " is never consumed");
   }
   if (!tk.word("END")) return fail(CHEM_ERR_PARSE, "missing END");
   return CHEM_OK;
@@ -341,6 +376,12 @@ int upload(chem_mech* h) {
   dm.csr_off = h->csr_off_np[np == 16 ? 0 : (np == 32 ? 1 : 2)];
   dm.nch = h->nch_np[np == 16 ? 0 : (np == 32 ? 1 : 2)];
   dm.csr_ent = reinterpret_cast<const int*>(base + o_ent);
+  if (!m.qss.empty()) {
+    // the state holds the transported species; QSS mechanisms run only in the
+    // generated kernels, which carry the closure themselves
+    dm.S = m.n_state_species();
+    dm.N = dm.S + 1;
+  }
   dm.nasa = nasa ? 1 : 0;
   dm.nasa_c = nasa ? reinterpret_cast<const double*>(base + o_nasa) : nullptr;
   dm.eff_k = reinterpret_cast<const int*>(base + o_effk);
@@ -411,6 +452,18 @@ namespace {
 int kernel_choice(const chem_mech* m, bool* lpc) {
   const int N = m->dev.N;
   bool want = false;
+  if (!m->host.qss.empty()) {
+    // the QSS closure is generated per mechanism: lane-per-cell kernels only
+    if (m->kernel_mode == 1)
+      return fail(CHEM_ERR_UNSUPPORTED, "mechanisms with QSS species run in the generated lane-per-cell kernels");
+    if (N > chemgpu::kLpcMaxN)
+      return fail(CHEM_ERR_UNSUPPORTED, "mechanisms with QSS species run in the generated kernels, which serve up to " +
+                                            std::to_string(chemgpu::kLpcMaxN) + " state components");
+    if (m->lu_fp32 || m->jac_mode)
+      return fail(CHEM_ERR_UNSUPPORTED, "the FP32-LU and difference-quotient options do not run with QSS species");
+    *lpc = true;
+    return CHEM_OK;
+  }
   if (m->kernel_mode == 2) {
     if (N > chemgpu::kLpcMaxN)
       return fail(CHEM_ERR_UNSUPPORTED,

@@ -13,7 +13,9 @@
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
+#include <algorithm>
 #include <cinttypes>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -59,6 +61,67 @@ std::string product(const std::vector<int>& sp, int skip) {
   return s.empty() ? "1.0" : s;
 }
 
+// Strongly connected components of the QSS dependency graph (App. B), in
+// the order they can be solved.  QSS species q depends on n when the closure
+// entry A_qn is structurally nonzero: n is the one QSS reactant of a kept
+// direction that changes q.  Tarjan's algorithm (one depth-first search with
+// discovery indices and low links) completes a component only after every
+// component it depends on, so its output order is the solve order.  Species
+// indices are the generator's internal ones (QSS species from ST on); nz
+// receives the structure [nq][nq].
+std::vector<std::vector<int>> qss_groups(const HostMech& m, int ST, std::vector<std::vector<char>>& nz) {
+  const int S = (int)m.W.size(), nq = S - ST;
+  nz.assign(nq, std::vector<char>(nq, 0));
+  for (const HostReaction& x : m.rx) {
+    std::vector<int> nu(S, 0);
+    for (int k : x.reac) nu[k] -= 1;
+    for (int k : x.prod) nu[k] += 1;
+    for (int dir = 0; dir < 2; ++dir) {
+      if (dir == 0 && x.drop_f) continue;
+      if (dir == 1 && (!x.rev || x.drop_r)) continue;
+      int n = -1;
+      for (int k : dir == 0 ? x.reac : x.prod)
+        if (k >= ST) n = k - ST;
+      if (n < 0) continue;
+      for (int q = 0; q < nq; ++q)
+        if (nu[ST + q]) nz[q][n] = 1;
+    }
+  }
+  std::vector<std::vector<int>> out;
+  std::vector<int> index(nq, -1), low(nq, 0), stack;
+  std::vector<char> on(nq, 0);
+  int counter = 0;
+  std::function<void(int)> visit = [&](int v) {
+    index[v] = low[v] = counter++;
+    stack.push_back(v);
+    on[v] = 1;
+    for (int w = 0; w < nq; ++w) {
+      if (w == v || !nz[v][w]) continue;
+      if (index[w] < 0) {
+        visit(w);
+        low[v] = std::min(low[v], low[w]);
+      } else if (on[w]) {
+        low[v] = std::min(low[v], index[w]);
+      }
+    }
+    if (low[v] == index[v]) {
+      std::vector<int> comp;
+      int w;
+      do {
+        w = stack.back();
+        stack.pop_back();
+        on[w] = 0;
+        comp.push_back(w);
+      } while (w != v);
+      std::sort(comp.begin(), comp.end());
+      out.push_back(comp);
+    }
+  };
+  for (int v = 0; v < nq; ++v)
+    if (index[v] < 0) visit(v);
+  return out;
+}
+
 void emit_nu_update(std::ostringstream& o, const char* arr, int k, int nu, const std::string& v) {
   if (nu == 1) o << "    " << arr << "[" << k << "] += " << v << ";\n";
   else if (nu == -1) o << "    " << arr << "[" << k << "] -= " << v << ";\n";
@@ -67,8 +130,37 @@ void emit_nu_update(std::ostringstream& o, const char* arr, int k, int nu, const
 
 }  // namespace
 
-std::string lpc_source(const HostMech& m, bool reuse) {
-  const int S = (int)m.W.size(), R = (int)m.rx.size(), N = S + 1;
+std::string lpc_source(const HostMech& m_in, bool reuse) {
+  // With QSS species the generated code numbers the species internally with
+  // the transported ones first (in their order, so that internal index =
+  // state index) and the QSS ones after them; without, the numbering is the
+  // mechanism's own.
+  const int S = (int)m_in.W.size(), R = (int)m_in.rx.size();
+  const int nq = (int)m_in.qss.size(), ST = S - nq, N = ST + 1;
+  std::vector<int> order, inv(S, -1);
+  {
+    std::vector<char> isq(S, 0);
+    for (int k : m_in.qss) isq[k] = 1;
+    for (int k = 0; k < S; ++k)
+      if (!isq[k]) order.push_back(k);
+    for (int k : m_in.qss) order.push_back(k);
+    for (int i = 0; i < S; ++i) inv[order[i]] = i;
+  }
+  HostMech m = m_in;
+  for (int i = 0; i < S; ++i) {
+    const int k = order[i];
+    m.W[i] = m_in.W[k];
+    m.a0[i] = m_in.a0[k];
+    m.a1[i] = m_in.a1[k];
+    m.hf[i] = m_in.hf[k];
+    m.s0[i] = m_in.s0[k];
+    m.nasa[i] = m_in.nasa[k];
+  }
+  for (HostReaction& x : m.rx) {
+    for (int& k : x.reac) k = inv[k];
+    for (int& k : x.prod) k = inv[k];
+    for (int& k : x.eff_k) k = inv[k];
+  }
   // Mechanism parameters are read from a __constant__ table (scalar loads,
   // several constants per instruction) rather than written as literals, each
   // of which costs two scalar moves wherever it is used.
@@ -141,17 +233,17 @@ std::string lpc_source(const HostMech& m, bool reuse) {
   for (int k = 0; k < S; ++k)
     if (isN(k)) o << "  const bool lo" << k << " = T <= " << kc(m.nasa[k][0]) << ";\n";
   o << "  double sumYW = 0.0;\n";
-  for (int k = 0; k < S; ++k) o << "  sumYW += y[" << k << "] * " << kc(1.0 / m.W[k]) << ";\n";
+  for (int k = 0; k < ST; ++k) o << "  sumYW += y[" << k << "] * " << kc(1.0 / m.W[k]) << ";\n";
   o << "  const double Wbar = 1.0 / sumYW;\n";
   o << "  const double rho = (p * 10.0) * Wbar / (CH_RU_CGS * T);\n";
   o << "  const double irho = 1.0 / rho;\n";
-  o << "  double C[CH_S];\n  double Mc = 0.0;\n";
-  for (int k = 0; k < S; ++k) o << "  C[" << k << "] = rho * y[" << k << "] * " << kc(1.0 / m.W[k]) << ";\n";
-  for (int k = 0; k < S; ++k) o << "  Mc += C[" << k << "];\n";
+  o << "  double C[CH_SA];\n  double Mc = 0.0;\n";
+  for (int k = 0; k < ST; ++k) o << "  C[" << k << "] = rho * y[" << k << "] * " << kc(1.0 / m.W[k]) << ";\n";
+  for (int k = 0; k < ST; ++k) o << "  Mc += C[" << k << "];\n";
   o << "  const double lnTr = log(T * " << kc(1.0 / kTref) << ");\n";
   o << "  const double invRT = 1.0 / (CH_RU * T);\n";
   o << "  const double lnc0 = log(CH_PATM * invRT * 1.0e-6);\n";
-  o << "  double H[CH_S], G[CH_S];\n";
+  o << "  double H[CH_SA], G[CH_SA];\n";
   o << "  if (JAC) {\n";
   for (int k = 0; k < S; ++k) o << "    H[" << k << "] = " << Hk(k) << ";\n";
   o << "  }\n";
@@ -167,20 +259,11 @@ std::string lpc_source(const HostMech& m, bool reuse) {
       o << "  G[" << k << "] = 0.0;\n";
   }
   o << "  (void)lnc0; (void)invRT; (void)lnT; (void)Mc;\n";
-  o << "  double wd[CH_S];\n";
-  // For JAC the species block of J first accumulates A = d wdot / dC at fixed
-  // T (without the [M] rank-one part, kept in ak) and is turned into the
-  // (Y, T) Jacobian in place at the end.
-  o << "  double bT[CH_S], ak[CH_S];\n";
-  o << "#pragma unroll\n  for (int k = 0; k < CH_S; ++k) {\n    wd[k] = 0.0;\n    bT[k] = 0.0;\n    ak[k] = 0.0;\n"
-       "    if (JAC) {\n#pragma unroll\n      for (int c = 0; c < CH_S; ++c) J[k][c] = 0.0;\n    }\n  }\n";
-  for (int j = 0; j < R; ++j) {
-    const HostReaction& x = m.rx[j];
-    std::vector<int> nu(S, 0);
-    for (int k : x.reac) nu[k] -= 1;
-    for (int k : x.prod) nu[k] += 1;
-    const int dnu = (int)x.prod.size() - (int)x.reac.size();
-    o << "  asm volatile(\"\" : \"+s\"(K));\n  {  // reaction " << j << "\n";
+  // Rate constants of reaction x (Eq. 2's k vector): k_f (with falloff and
+  // Troe's factor) and, for reversible reactions, k_r from K_c; with JAC their
+  // T and [M] derivatives.  Emitted in two parts around the reactant and
+  // product concentration products.
+  auto emit_kf = [&](const HostReaction& x) {
     o << "    const double kinf = ch_exp(" << kc(std::log(x.A)) << " + " << kc(x.b) << " * lnT - "
       << kc(x.Ea * kcal_to_K) << " * invT);\n";
     o << "    double kf = kinf;\n";
@@ -190,7 +273,7 @@ std::string lpc_source(const HostMech& m, bool reuse) {
     if (x.type != 0) {
       o << "    const double Mj = Mc";
       for (size_t i = 0; i < x.eff_k.size(); ++i)
-        o << " + " << kc(x.eff_v[i] - 1.0) << " * " << C(x.eff_k[i]);
+        if (x.eff_k[i] < ST) o << " + " << kc(x.eff_v[i] - 1.0) << " * " << C(x.eff_k[i]);
       o << ";\n";
     }
     if (x.type == 2) {
@@ -233,8 +316,8 @@ std::string lpc_source(const HostMech& m, bool reuse) {
         o << "      kf *= F;\n    }\n";
       }
     }
-    o << "    const double pf = " << product(x.reac, -1) << ";\n";
-    o << "    const double pr = " << product(x.prod, -1) << ";\n";
+  };
+  auto emit_kr = [&](const HostReaction& x, const std::vector<int>& nu, int dnu) {
     o << "    double kr = 0.0, dkr = 0.0, dkrdM = 0.0;\n    (void)dkr; (void)dkrdM;\n";
     if (x.rev) {
       // sum_k nu_k G_k / RT and sum_k nu_k H_k over the net stoichiometry
@@ -257,49 +340,188 @@ std::string lpc_source(const HostMech& m, bool reuse) {
       o << "      dkr = kr * (dlnkf - dlnKc);\n";
       o << "      dkrdM = dkfdM * ratio;\n    }\n";
     }
+  };
+  auto nu_of = [&](const HostReaction& x) {
+    std::vector<int> nu(S, 0);
+    for (int k : x.reac) nu[k] -= 1;
+    for (int k : x.prod) nu[k] += 1;
+    return nu;
+  };
+  // row k of the concentration-space Jacobian: transported rows accumulate in
+  // J (state block) or, for a QSS column, in ATQ; QSS rows in AQT
+  auto jac_row = [&](int k, int c) -> std::string {
+    if (k < ST) return c < ST ? "    J[" + std::to_string(k) + "]" : "    ATQ[" + std::to_string(k) + "]";
+    return "    AQT[" + std::to_string(k - ST) + "]";
+  };
+  auto jac_col = [&](int c) { return c < ST ? c : c - ST; };
+  // QSS groups in solve order, and which closure entries are structurally nonzero
+  std::vector<std::vector<char>> nzA;
+  const std::vector<std::vector<int>> groups = qss_groups(m, ST, nzA);
+  std::vector<int> group_of(nq, -1);
+  for (size_t gi = 0; gi < groups.size(); ++gi)
+    for (int q : groups[gi]) group_of[q] = (int)gi;
+  if (nq > 0) {
+    // QSS closure (Eq. 4-6): with the quadratic couplings removed each kept
+    // direction carries at most one QSS concentration as a factor, so the QSS
+    // production rates are affine, qA C_Q - qb; the system is solved group by
+    // group in the dependency order of its strongly connected components
+    // (App. B), found with Tarjan's algorithm when the source is generated.
+    o << "  double qA[CH_NQ][CH_NQ], qb[CH_NQ];\n";
+    o << "#pragma unroll\n  for (int a = 0; a < CH_NQ; ++a) {\n    qb[a] = 0.0;\n"
+         "#pragma unroll\n    for (int b = 0; b < CH_NQ; ++b) qA[a][b] = 0.0;\n  }\n";
+    for (int j = 0; j < R; ++j) {
+      const HostReaction& x = m.rx[j];
+      const std::vector<int> nu = nu_of(x);
+      bool touches = false;
+      for (int k = ST; k < S; ++k) touches |= nu[k] != 0;
+      if (!touches) continue;
+      const int dnu = (int)x.prod.size() - (int)x.reac.size();
+      o << "  asm volatile(\"\" : \"+s\"(K));\n  {  // closure terms of reaction " << j << "\n";
+      emit_kf(x);
+      emit_kr(x, nu, dnu);
+      o << "    const double mf = " << (x.type == 1 ? "Mj" : "1.0") << ";\n";
+      for (int dir = 0; dir < 2; ++dir) {
+        if (dir == 0 && x.drop_f) continue;
+        if (dir == 1 && (!x.rev || x.drop_r)) continue;
+        const std::vector<int>& side = dir == 0 ? x.reac : x.prod;
+        int n = -1;
+        std::string c = dir == 0 ? "mf * kf" : "mf * kr";
+        for (int k : side) {
+          if (k >= ST) n = k - ST;
+          else c += " * " + C(k);
+        }
+        o << "    {\n      const double cq = " << c << ";\n";
+        for (int k = ST; k < S; ++k) {
+          if (!nu[k]) continue;
+          const int sgn = dir == 0 ? nu[k] : -nu[k];
+          const std::string v = (sgn == 1 ? "" : (sgn == -1 ? "-" : lit((double)sgn) + " * ")) + std::string("cq");
+          if (n >= 0) o << "      qA[" << k - ST << "][" << n << "] += " << v << ";\n";
+          else o << "      qb[" << k - ST << "] -= " << v << ";\n";
+        }
+        o << "    }\n";
+      }
+      o << "  }\n";
+    }
+    o << "  asm volatile(\"\" : \"+s\"(K));\n";
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      const std::vector<int>& g = groups[gi];
+      const int n = (int)g.size();
+      o << "  {  // QSS group";
+      for (int q : g) o << " " << q;
+      o << "\n    double a[" << n << "][" << n << "], r[" << n << "][1];\n";
+      for (int i = 0; i < n; ++i) {
+        for (int jj = 0; jj < n; ++jj) o << "    a[" << i << "][" << jj << "] = qA[" << g[i] << "][" << g[jj] << "];\n";
+        o << "    r[" << i << "][0] = qb[" << g[i] << "]";
+        for (int q = 0; q < nq; ++q)
+          if (group_of[q] < (int)gi && nzA[g[i]][q]) o << " - qA[" << g[i] << "][" << q << "] * C[" << ST + q << "]";
+        o << ";\n";
+      }
+      o << "    ch_gauss<" << n << ", 1>(a, r);\n";
+      for (int i = 0; i < n; ++i) o << "    C[" << ST + g[i] << "] = r[" << i << "][0];\n";
+      o << "  }\n";
+    }
+  }
+  o << "  double wd[CH_S];\n";
+  // For JAC the species block of J first accumulates A = d wdot / dC at fixed
+  // T (without the [M] rank-one part, kept in ak) and is turned into the
+  // (Y, T) Jacobian in place at the end.
+  o << "  double bT[CH_S], ak[CH_S];\n";
+  o << "#pragma unroll\n  for (int k = 0; k < CH_S; ++k) {\n    wd[k] = 0.0;\n    bT[k] = 0.0;\n    ak[k] = 0.0;\n"
+       "    if (JAC) {\n#pragma unroll\n      for (int c = 0; c < CH_S; ++c) J[k][c] = 0.0;\n    }\n  }\n";
+  if (nq > 0) {
+    // blocks of the concentration-space Jacobian that involve QSS species
+    o << "  double ATQ[CH_S][CH_NQ], AQT[CH_NQ][CH_S], bTQ[CH_NQ], akQ[CH_NQ];\n";
+    o << "  if (JAC) {\n#pragma unroll\n    for (int a = 0; a < CH_NQ; ++a) {\n      bTQ[a] = 0.0;\n      akQ[a] = 0.0;\n"
+         "#pragma unroll\n      for (int k = 0; k < CH_S; ++k) {\n        ATQ[k][a] = 0.0;\n        AQT[a][k] = 0.0;\n"
+         "      }\n    }\n  }\n";
+  }
+  for (int j = 0; j < R; ++j) {
+    const HostReaction& x = m.rx[j];
+    const std::vector<int> nu = nu_of(x);
+    const int dnu = (int)x.prod.size() - (int)x.reac.size();
+    o << "  asm volatile(\"\" : \"+s\"(K));\n  {  // reaction " << j << "\n";
+    emit_kf(x);
+    // a direction removed by the linearisation has a zero concentration product
+    o << "    const double pf = " << (x.drop_f ? std::string("0.0") : product(x.reac, -1)) << ";\n";
+    o << "    const double pr = " << (x.drop_r ? std::string("0.0") : product(x.prod, -1)) << ";\n";
+    emit_kr(x, nu, dnu);
     o << "    const double mf = " << (x.type == 1 ? "Mj" : "1.0") << ";\n";
     o << "    const double net = kf * pf - kr * pr;\n";
     o << "    const double Q = mf * net;\n";
-    for (int k = 0; k < S; ++k)
+    for (int k = 0; k < ST; ++k)
       if (nu[k]) emit_nu_update(o, "wd", k, nu[k], "Q");
     o << "    if (JAC) {\n";
     o << "      const double dQdT = mf * (kf * dlnkf * pf - dkr * pr);\n";
     for (int k = 0; k < S; ++k)
-      if (nu[k]) emit_nu_update(o, "  bT", k, nu[k], "dQdT");
+      if (nu[k]) emit_nu_update(o, k < ST ? "  bT" : "  bTQ", jac_col(k), nu[k], "dQdT");
     if (x.type == 1 || x.type == 2) {
       o << "      const double q0 = " << (x.type == 1 ? "net" : "dkfdM * pf - dkrdM * pr") << ";\n";
       for (int k = 0; k < S; ++k)
-        if (nu[k]) emit_nu_update(o, "  ak", k, nu[k], "q0");
+        if (nu[k]) emit_nu_update(o, k < ST ? "  ak" : "  akQ", jac_col(k), nu[k], "q0");
       // efficiencies other than 1: d[M]_j/dC_c = 1 + (eps_c - 1), the 1 being the rank-one part in ak
       for (size_t i = 0; i < x.eff_k.size(); ++i) {
+        if (x.eff_k[i] >= ST) continue;     // QSS species do not collide
         o << "      {\n        const double dq = q0 * " << kc(x.eff_v[i] - 1.0) << ";\n";
         for (int k = 0; k < S; ++k)
-          if (nu[k]) emit_nu_update(o, ("    J[" + std::to_string(k) + "]").c_str(), x.eff_k[i], nu[k], "dq");
+          if (nu[k]) emit_nu_update(o, jac_row(k, x.eff_k[i]).c_str(), x.eff_k[i], nu[k], "dq");
         o << "      }\n";
       }
     }
-    for (size_t s = 0; s < x.reac.size(); ++s) {
-      o << "      {\n        const double dq = mf * kf * " << product(x.reac, (int)s) << ";\n";
+    for (size_t sl = 0; sl < x.reac.size() && !x.drop_f; ++sl) {
+      const int c = x.reac[sl];
+      o << "      {\n        const double dq = mf * kf * " << product(x.reac, (int)sl) << ";\n";
       for (int k = 0; k < S; ++k)
-        if (nu[k]) emit_nu_update(o, ("    J[" + std::to_string(k) + "]").c_str(), x.reac[s], nu[k], "dq");
+        if (nu[k] && !(k >= ST && c >= ST)) emit_nu_update(o, jac_row(k, c).c_str(), jac_col(c), nu[k], "dq");
       o << "      }\n";
     }
-    for (size_t s = 0; s < x.prod.size(); ++s) {
-      o << "      {\n        const double dq = -mf * kr * " << product(x.prod, (int)s) << ";\n";
+    for (size_t sl = 0; sl < x.prod.size() && !x.drop_r; ++sl) {
+      const int c = x.prod[sl];
+      o << "      {\n        const double dq = -mf * kr * " << product(x.prod, (int)sl) << ";\n";
       for (int k = 0; k < S; ++k)
-        if (nu[k]) emit_nu_update(o, ("    J[" + std::to_string(k) + "]").c_str(), x.prod[s], nu[k], "dq");
+        if (nu[k] && !(k >= ST && c >= ST)) emit_nu_update(o, jac_row(k, c).c_str(), jac_col(c), nu[k], "dq");
       o << "      }\n";
     }
     o << "    }\n  }\n";
   }
+  if (nq > 0) {
+    // Jacobian through the closure (Sec. 3.2): the QSS concentrations follow
+    // the transported ones and T, so with X = qA^-1 [A_QT | b_Q] the state
+    // block becomes A_TT - A_TQ X and the T column b_T - A_TQ X_T
+    o << "  if (JAC) {\n    double X[CH_NQ][CH_N];\n";
+    o << "#pragma unroll\n    for (int a = 0; a < CH_NQ; ++a) {\n"
+         "#pragma unroll\n      for (int c = 0; c < CH_S; ++c) X[a][c] = AQT[a][c] + akQ[a];\n"
+         "      X[a][CH_S] = bTQ[a];\n    }\n";
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      const std::vector<int>& g = groups[gi];
+      const int n = (int)g.size();
+      o << "    {  // QSS group";
+      for (int q : g) o << " " << q;
+      o << "\n      double a[" << n << "][" << n << "], r[" << n << "][CH_N];\n";
+      for (int i = 0; i < n; ++i) {
+        for (int jj = 0; jj < n; ++jj) o << "      a[" << i << "][" << jj << "] = qA[" << g[i] << "][" << g[jj] << "];\n";
+        o << "#pragma unroll\n      for (int c = 0; c < CH_N; ++c) r[" << i << "][c] = X[" << g[i] << "][c]";
+        for (int q = 0; q < nq; ++q)
+          if (group_of[q] < (int)gi && nzA[g[i]][q]) o << " - qA[" << g[i] << "][" << q << "] * X[" << q << "][c]";
+        o << ";\n";
+      }
+      o << "      ch_gauss<" << n << ", CH_N>(a, r);\n";
+      for (int i = 0; i < n; ++i)
+        o << "#pragma unroll\n      for (int c = 0; c < CH_N; ++c) X[" << g[i] << "][c] = r[" << i << "][c];\n";
+      o << "    }\n";
+    }
+    o << "#pragma unroll\n    for (int k = 0; k < CH_S; ++k) {\n"
+         "#pragma unroll\n      for (int a = 0; a < CH_NQ; ++a) {\n"
+         "#pragma unroll\n        for (int c = 0; c < CH_S; ++c) J[k][c] -= ATQ[k][a] * X[a][c];\n"
+         "        bT[k] -= ATQ[k][a] * X[a][CH_S];\n      }\n    }\n  }\n";
+  }
   // right-hand side
   o << "  double num = 0.0, den = 0.0;\n";
-  for (int k = 0; k < S; ++k) {
+  for (int k = 0; k < ST; ++k) {
     o << "  num += (JAC ? H[" << k << "] : " << Hk(k) << ") * wd[" << k << "];\n";
     o << "  den += C[" << k << "] * " << Cpk(k) << ";\n";
   }
   o << "  const double iden = 1.0 / den;\n";
-  for (int k = 0; k < S; ++k) o << "  f[" << k << "] = " << kc(m.W[k]) << " * wd[" << k << "] * irho;\n";
+  for (int k = 0; k < ST; ++k) o << "  f[" << k << "] = " << kc(m.W[k]) << " * wd[" << k << "] * irho;\n";
   o << "  f[CH_S] = fixedT ? 0.0 : -num * iden;\n";
   o << "  if (WD) {\n#pragma unroll\n    for (int k = 0; k < CH_S; ++k) wdo[k] = wd[k];\n  }\n";
   // Jacobian: row sums AC_k = sum_c A_kc C_c and the temperature row (which
@@ -310,14 +532,14 @@ std::string lpc_source(const HostMech& m, bool reuse) {
        "#pragma unroll\n      for (int c = 0; c < CH_S; ++c) s += (J[k][c] + ak[k]) * C[c];\n"
        "      AC[k] = s;\n      dwdT[k] = bT[k] - s * invT;\n    }\n";
   o << "    double iW[CH_S], Wk[CH_S], Cp[CH_S];\n";
-  for (int k = 0; k < S; ++k) o << "    Cp[" << k << "] = " << Cpk(k) << ";\n";
-  for (int k = 0; k < S; ++k) o << "    iW[" << k << "] = " << kc(1.0 / m.W[k]) << ";\n";
-  for (int k = 0; k < S; ++k) o << "    Wk[" << k << "] = " << kc(m.W[k]) << ";\n";
+  for (int k = 0; k < ST; ++k) o << "    Cp[" << k << "] = " << Cpk(k) << ";\n";
+  for (int k = 0; k < ST; ++k) o << "    iW[" << k << "] = " << kc(1.0 / m.W[k]) << ";\n";
+  for (int k = 0; k < ST; ++k) o << "    Wk[" << k << "] = " << kc(m.W[k]) << ";\n";
   o << "    if (fixedT) {\n#pragma unroll\n      for (int c = 0; c < CH_N; ++c) J[CH_S][c] = 0.0;\n    } else {\n";
   o << "      double HAC = 0.0, HdwdT = 0.0, Cpw = 0.0, Ca1 = 0.0;\n";
   o << "#pragma unroll\n      for (int k = 0; k < CH_S; ++k) {\n        HAC += H[k] * AC[k];\n"
        "        HdwdT += H[k] * dwdT[k];\n        Cpw += Cp[k] * wd[k];\n      }\n";
-  for (int k = 0; k < S; ++k) o << "      Ca1 += C[" << k << "] * " << dCpk(k) << ";\n";
+  for (int k = 0; k < ST; ++k) o << "      Ca1 += C[" << k << "] * " << dCpk(k) << ";\n";
   o << "#pragma unroll\n      for (int c = 0; c < CH_S; ++c) {\n        double colsum = 0.0;\n"
        "#pragma unroll\n        for (int k = 0; k < CH_S; ++k) colsum += H[k] * (J[k][c] + ak[k]);\n"
        "        const double dN = (rho * iW[c]) * colsum - (Wbar * iW[c]) * HAC;\n"
@@ -334,7 +556,28 @@ std::string lpc_source(const HostMech& m, bool reuse) {
   std::ostringstream head;
   head << "// generated: lane-per-cell kernels for a mechanism with " << S << " species and " << R
        << " reactions\n";
-  head << "#define CH_S " << S << "\n#define CH_N " << N << "\n";
+  head << "#define CH_S " << ST << "\n#define CH_N " << N << "\n#define CH_SA " << S << "\n";
+  if (nq > 0) {
+    head << "#define CH_NQ " << nq << "\n";
+    // dense solve of one QSS group: Gaussian elimination with partial
+    // pivoting (a row moves up only when strictly larger in magnitude), NR
+    // right-hand sides, solution left in r
+    head << "template <int K, int NR>\n__device__ __forceinline__ void ch_gauss(double (&a)[K][K], double (&r)[K][NR]) {\n"
+            "#pragma unroll\n  for (int c = 0; c < K; ++c) {\n"
+            "#pragma unroll\n    for (int i = c + 1; i < K; ++i) {\n"
+            "      const bool sw = fabs(a[i][c]) > fabs(a[c][c]);\n"
+            "#pragma unroll\n      for (int j = c; j < K; ++j) {\n        const double t = a[c][j];\n"
+            "        a[c][j] = sw ? a[i][j] : t;\n        a[i][j] = sw ? t : a[i][j];\n      }\n"
+            "#pragma unroll\n      for (int q = 0; q < NR; ++q) {\n        const double t = r[c][q];\n"
+            "        r[c][q] = sw ? r[i][q] : t;\n        r[i][q] = sw ? t : r[i][q];\n      }\n    }\n"
+            "#pragma unroll\n    for (int i = c + 1; i < K; ++i) {\n      const double l = a[i][c] / a[c][c];\n"
+            "#pragma unroll\n      for (int j = c + 1; j < K; ++j) a[i][j] -= l * a[c][j];\n"
+            "#pragma unroll\n      for (int q = 0; q < NR; ++q) r[i][q] -= l * r[c][q];\n    }\n  }\n"
+            "#pragma unroll\n  for (int i = K - 1; i >= 0; --i) {\n"
+            "#pragma unroll\n    for (int q = 0; q < NR; ++q) {\n      double sum = r[i][q];\n"
+            "#pragma unroll\n      for (int j = i + 1; j < K; ++j) sum -= a[i][j] * r[j][q];\n"
+            "      r[i][q] = sum / a[i][i];\n    }\n  }\n}\n";
+  }
   // Newton-matrix reuse is compiled in only when asked for: keeping the
   // factors across attempts holds them in registers through the whole step
   head << "#define CH_REUSE " << (reuse ? 1 : 0) << "\n";

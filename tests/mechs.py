@@ -48,7 +48,7 @@ def mixed_kinds():
     return tiny(sp, rx)
 
 
-def qss_tiny(low=(1e16, 0.0, 2.0), speed=1.0, coupling=True, dh_qss=0.0):
+def qss_tiny(low=(1e16, 0.0, 2.0), speed=1.0, coupling=True, dh_qss=0.0, third=False):
     """Six transported species, two QSS species X and Y and an inert, over
     the elements H and C, built so that every part of the closure is
     exercised: a QSS group of two (X and Y turn into each other through
@@ -61,7 +61,11 @@ def qss_tiny(low=(1e16, 0.0, 2.0), speed=1.0, coupling=True, dh_qss=0.0):
     replaces reaction 2 by A + C = X + E and leaves out reaction 6: no
     quadratic coupling, nothing linearised (and X, Y do not collide).
     dh_qss raises the formation enthalpies of X and Y (J/mol): less stable,
-    scarcer and shorter-lived, while the flux through them stays."""
+    scarcer and shorter-lived, while the flux through them stays.
+    third=True adds a third QSS species Z, made from X (X + B -> Z) and
+    leaking into A + Z = C + E: a group of its own that depends on the X, Y
+    group; it is listed first in the QSS record, so its solve order comes
+    from the dependencies, not from the record."""
     sp = [("A", (2, 0), 3.5, 2e-4, 0.0, 130.0, False),
           ("B", (0, 2), 3.6, 1e-4, 0.0, 200.0, False),
           ("C", (1, 1), 4.0, 2e-4, 40000.0, 200.0, False),
@@ -90,6 +94,9 @@ def qss_tiny(low=(1e16, 0.0, 2.0), speed=1.0, coupling=True, dh_qss=0.0):
             r.A *= speed
             if r.low is not None:
                 r.low = (r.low[0] * speed, r.low[1], r.low[2])
+    if third:
+        sp.insert(7, ("Z", (1, 2), 3.0, 1e-4, 150000.0, 200.0, False))
+        rx += [R([X, B], [7], 3e12, 0.0, 2.0, False), R([7, A], [C, E], 1e13, 0.0, 3.0)]
     if not coupling:
         rx[1] = R([A, C], [X, E], 1e11, 0.0, 40.0)
         # X and Y collide with efficiency 0, so that [M] is the same whether
@@ -98,5 +105,5 @@ def qss_tiny(low=(1e16, 0.0, 2.0), speed=1.0, coupling=True, dh_qss=0.0):
         rx[9].eff = {A: 2.0, X: 0.0, Y: 0.0}
         del rx[5]
     m = tiny(sp, rx)
-    m.qss = [X, Y]
+    m.qss = [7, X, Y] if third else [X, Y]
     return m

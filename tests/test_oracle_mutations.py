@@ -336,7 +336,13 @@ def pin_qss_numpy(lib):
     reads the closure matrix off its own affine QSS production rates, and
     complex-step derivatives of it; on the hand-built QSS mechanism with its
     quadratic couplings, below and above 1000 K and at two pressures."""
-    m = mechs.qss_tiny()
+    for third in (False, True):
+        if not _qss_numpy_case(lib, mechs.qss_tiny(third=third)):
+            return False
+    return True
+
+
+def _qss_numpy_case(lib, m):
     om = oracle.Mech(m.to_text(), lib_path=lib)
     rng = np.random.default_rng(3)
     for T in (800.0, 1400.0, 2200.0):
