@@ -80,7 +80,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=8192, help="cells in the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--q-max", type=int, default=5)
-    ap.add_argument("--mode", choices=["flame", "boxes", "serve", "copy", "jacstudy", "sweep", "peak"],
+    ap.add_argument("--mode", choices=["flame", "boxes", "serve", "copy", "jacstudy", "sweep", "peak", "mfma"],
                     default="flame",
                     help="flame: the headline box; boxes: uneven AMR boxes in one persistent launch; "
                          "serve: Poisson request trace through the continuous-batching server; "
@@ -115,6 +115,8 @@ def main():
         return copy_calibration(torch, dev)
     if args.mode == "peak":
         return probe_peak(torch)
+    if args.mode == "mfma":
+        return probe_mfma(synth)
     if args.mode == "boxes":
         return bench_boxes(args, torch, dev, chem, synth)
     if args.mode == "serve":
@@ -408,6 +410,58 @@ def probe_peak(torch):
     out["what"] = ("fma: 16 independent FMA chains per thread, 8192 blocks of 256 threads, 2048 trips; "
                    "exp probes: 2048 blocks of 256 threads, 4096 exps per thread, arguments in [-60, -19]")
     print(json.dumps(out), flush=True)
+
+
+def probe_mfma(synth):
+    """The production-rate contraction wdot = Q nu^T of the 10- and
+    53-species mechanisms, as the dense [cells x R] x [R x S] product on FP64
+    matrix cores (v_mfma_f64_16x16x4) and as the sparse per-species gather of
+    the kernels, rates of progress generated in registers in both
+    (libchem_probe.so).  Each result is checked against numpy on 100 cells
+    first; then both are timed on a full box of cells, 64 contractions per
+    cell per launch (so that writing the result does not dominate)."""
+    import ctypes as C
+    lib = C.CDLL(os.path.join(ROOT, "paper_2405_05974_amd", "libchem_probe.so"))
+    lib.chem_probe_wdot.argtypes = [C.c_char_p, C.POINTER(C.c_int), C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    iters = 64
+    res = {"mode": "mfma", "what": probe_mfma.__doc__.split("\n\n")[0].replace("\n    ", " ")}
+    for cfg, ncells in ((2, 1 << 20), (3, 1 << 18)):
+        m = synth.config_mechanism(cfg)
+        S, R = m.n_species, m.n_reactions
+        nu = np.zeros((R, S), dtype=np.int32)
+        for j, r in enumerate(m.reactions):
+            for k in r.reactants:
+                nu[j, k] -= 1
+            for k in r.products:
+                nu[j, k] += 1
+        nup = np.ascontiguousarray(nu).ctypes.data_as(C.POINTER(C.c_int))
+        nchk = 100
+        Q = 1.0 + 1e-6 * np.arange(nchk)[:, None] + 1e-3 * np.arange(R)[None, :]
+        ref = Q @ nu.astype(float)
+        row = {"species": S, "reactions": R, "cells": ncells, "nnz": int(np.count_nonzero(nu)),
+               "dense_padded": [(R + 3) // 4 * 4, (S + 15) // 16 * 16]}
+        for which in ("mfma", "sparse"):
+            out = np.zeros((nchk, S))
+            ms = C.c_double()
+            if lib.chem_probe_wdot(which.encode(), nup, R, S, nchk, 1, 1, out.ctypes.data_as(C.POINTER(C.c_double)),
+                                   C.byref(ms)) != 0:
+                raise RuntimeError(f"{which} probe failed")
+            err = float(np.abs(out - ref).max() / np.abs(ref).max())
+            if err > 1e-13:
+                raise RuntimeError(f"{which} probe wrong: {err}")
+            if lib.chem_probe_wdot(which.encode(), nup, R, S, ncells, iters, 5, None, C.byref(ms)) != 0:
+                raise RuntimeError(f"{which} probe failed")
+            row[which] = {"ms": ms.value, "ns_per_contraction": ms.value * 1e6 / (ncells * iters),
+                          "check_rel_err": err}
+            print(f"mfma probe: G{cfg} {which}: {ms.value:.3f} ms for {ncells} cells", file=sys.stderr, flush=True)
+        RP, SP = row["dense_padded"]
+        row["contractions_per_cell"] = iters
+        row["flops_per_contraction"] = {"mfma_executed": 2 * RP * SP, "sparse_algorithmic": 2 * row["nnz"]}
+        row["mfma_tflops_executed"] = 2 * RP * SP * ncells * iters / (row["mfma"]["ms"] * 1e-3) / 1e12
+        row["mfma_over_sparse_time"] = row["mfma"]["ms"] / row["sparse"]["ms"]
+        res[f"G{m.n_species}_{m.n_reactions}"] = row
+    print(json.dumps(res), flush=True)
 
 
 def bench_boxes(args, torch, dev, chem, synth):
