@@ -96,10 +96,14 @@ def main():
                     help="kernel family: lane = generated lane-per-cell kernels (S+1 <= 12), group = 16-64 lanes "
                          "per cell; auto picks lane where it applies")
     ap.add_argument("--n-boxes", type=int, default=200)
-    ap.add_argument("--max-box-cells", type=int, default=4096)
-    ap.add_argument("--rate", type=float, default=20.0,
+    ap.add_argument("--max-box-cells", type=int, default=None,
+                    help="boxes/serve: cap on the cells of one box (default: none, edges up to 64)")
+    ap.add_argument("--rate", type=float, default=2000.0,
                     help="serve: arrivals per second (the full trace's 2000/s is far beyond one GPU's capacity)")
-    ap.add_argument("--duration", type=float, default=10.0, help="serve: trace length, s")
+    ap.add_argument("--duration", type=float, default=60.0, help="serve: trace length, s")
+    ap.add_argument("--wall", type=float, default=150.0, help="serve: stop after this many seconds")
+    ap.add_argument("--queue-gb", type=float, default=8.0,
+                    help="serve: request state the host keeps waiting for the server; more is refused")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -298,8 +302,6 @@ def cpu_baseline(w, Tg, Yg, args):
     import tempfile
     import oracle
     n = w.n_cells
-    k = max(1, min(args.cpu_sample, n))
-    idx = np.unique(np.linspace(0, n - 1, k).astype(np.int64))
     tmpdir = tempfile.mkdtemp(prefix="oracle_native_")
     try:
         lib_path = oracle.build_native(tmpdir)
@@ -309,6 +311,16 @@ def cpu_baseline(w, Tg, Yg, args):
         lib_path, build = None, "gcc -O3 -fopenmp -ffp-contract=off (portable build)"
     om = oracle.Mech(w.mech.to_text(), lib_path=lib_path)
     threads = oracle.max_threads()
+    # size the sample to about 15 s per run: a pilot of 2 cells per thread, strided over the box
+    pilot = np.unique(np.linspace(0, n - 1, min(n, 2 * threads)).astype(np.int64))
+    t0 = time.perf_counter()
+    om.integrate(w.T[pilot], w.Y[:, pilot], w.p, w.dt, w.rtol, w.atol, q_max=args.q_max, nthreads=threads,
+                 jac_reuse=args.jac_reuse, want_stats=False)
+    per_cell = (time.perf_counter() - t0) / pilot.size
+    k = int(max(threads, min(args.cpu_sample, n, 15.0 / max(per_cell, 1e-9))))
+    print(f"cpu baseline: pilot {pilot.size} cells in {per_cell * pilot.size:.1f} s; sample {k} cells",
+          file=sys.stderr, flush=True)
+    idx = np.unique(np.linspace(0, n - 1, k).astype(np.int64))
     runs = []
     for r in range(3):
         print(f"cpu baseline: oracle run {r + 1}/3 on {idx.size} cells, {threads} threads", file=sys.stderr, flush=True)
@@ -466,12 +478,13 @@ def probe_mfma(synth):
 
 def bench_boxes(args, torch, dev, chem, synth):
     """Uneven AMR boxes of G(30,180,4, seed 3) with per-box dt, one persistent
-    launch; edges log-uniform 8..64 cells, capped at --max-box-cells."""
+    launch; edges log-uniform 8..64 cells, capped at --max-box-cells when
+    given.  The library reports completed boxes every 20 s during a launch."""
     m = synth.config_mechanism(4)
     boxes = synth.amr_boxes(m, args.n_boxes, synth.config_seed(4), max_cells=args.max_box_cells)
     gm = chem.Mechanism(m.to_text())
     gm.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32), kernel=KERNEL_CODES[args.kernel],
-                   jac_reuse=int(args.jac_reuse))
+                   jac_reuse=int(args.jac_reuse), progress=20)
     src = [(torch.tensor(b.T, device=dev), torch.tensor(b.Y, device=dev), b.dt) for b in boxes]
     work = [(t.clone(), y.clone(), dt) for t, y, dt in src]
     sample_T = torch.cat([t[: min(256, t.numel())] for t, _, _ in src[:8]])
@@ -502,8 +515,9 @@ def bench_boxes(args, torch, dev, chem, synth):
         "steps": args.steps, "ms_per_step": el * 1e3, "dtype": "f64+f32lu" if args.lu_fp32 else "f64",
         "box_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                            "what": "launch to box completion, host-observed"},
-        "config": {"workload": f"{len(boxes)} boxes of G(30,180,4,seed 3), edges log-uniform 8..64 capped at "
-                               f"{args.max_box_cells} cells, per-box dt log-uniform 1e-7..1e-5 s, rtol 1e-8, "
+        "config": {"workload": f"{len(boxes)} boxes of G(30,180,4,seed 3), edges log-uniform 8..64"
+                               + (f" capped at {args.max_box_cells} cells" if args.max_box_cells else "")
+                               + ", per-box dt log-uniform 1e-7..1e-5 s, rtol 1e-8, "
                                + ("Newton matrix kept while recent" if args.jac_reuse else "fresh Newton matrix"),
                    "cells": n, "group_width": width, "waves_per_cu": waves},
         "integration": {"steps_per_cell": stats["n_steps_total"] / n, "failed_cells": stats["n_cells_failed"]},
@@ -596,51 +610,89 @@ def bench_sweep(args, torch, dev, chem, synth):
 
 
 def bench_serve(args, torch, dev, chem, synth):
-    """Poisson arrivals of box-solve requests, each drawing G(10,25,3,s1) or
-    G(53,325,4,s2) with p = 0.5 and an edge log-uniform in 8..64 cells
-    (capped at --max-box-cells); T, Y and dt as in the uneven-box workload."""
+    """The serving workload: Poisson arrivals at --rate req/s over --duration s
+    of box-solve requests, each drawing G(10,25,3,s1) or G(53,325,4,s2) with
+    p = 0.5 and a cubic box of edge log-uniform in 8..64 cells (capped at
+    --max-box-cells when given), T, Y and dt as in the uneven-box workload,
+    served under an HBM budget of --budget-gb.  A request's cells are drawn
+    when it arrives.  The host keeps at most --queue-gb of request state
+    waiting for the server; arrivals beyond that are refused at the door and
+    counted.  The run stops at --wall seconds; requests still queued or on the
+    GPU then are counted, not waited for.  Latency is trace arrival to results
+    on the host."""
     mechs_ = [synth.config_mechanism(2), synth.config_mechanism(3)]
     handles = [chem.Mechanism(m.to_text()) for m in mechs_]
     for h in handles:
         h.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32), jac_reuse=int(args.jac_reuse),
                       kernel=KERNEL_CODES[args.kernel] if h.N <= LANE_MAX_N or args.kernel != "lane" else 0)
     arrivals = synth.poisson_trace(1005, args.rate, args.duration)
-    rng = np.random.default_rng(1005)
-    reqs = []
-    for i, ta in enumerate(arrivals):
-        k = int(rng.integers(0, 2))
-        bx = synth.amr_boxes(mechs_[k], 1, 10_000 + i, max_cells=args.max_box_cells)[0]
-        reqs.append((ta, k, bx))
+    pick = np.random.default_rng(1005).integers(0, 2, size=arrivals.size)
     srv = chem.Server(int(args.budget_gb * (1 << 30)), streams=4)
-    pending, lat, cells = {}, [], 0
+    queue_cap = args.queue_gb * (1 << 30)
+    pending = {}                  # id -> (arrival s, cells, bytes)
+    lat, lat_by = [], {0: [], 1: []}
+    cells_done = accepted = refused = 0
+    held = 0.0
     t0 = time.perf_counter()
+    next_report = 10.0
     i = 0
-    while i < len(reqs) or pending:
+    while True:
         now = time.perf_counter() - t0
-        while i < len(reqs) and reqs[i][0] <= now:
-            ta, k, bx = reqs[i]
-            pending[srv.submit(handles[k], bx.T, bx.Y, synth.P_ATM, bx.dt, 1e-8, 1e-12)] = bx.T.size
+        if now >= args.wall or (i >= arrivals.size and not pending):
+            break
+        while i < arrivals.size and arrivals[i] <= now:
+            k = int(pick[i])
+            S = mechs_[k].n_species
+            # the box's edge is the first draw of its generator (synth.amr_boxes), so a refused
+            # request costs no cell generation
+            L = int(round(math.exp(np.random.default_rng(10_000 + i).uniform(math.log(8), math.log(64)))))
+            n_est = L ** 3 if args.max_box_cells is None else min(L ** 3, args.max_box_cells)
+            nbytes = 8.0 * (S + 1) * n_est
+            if held + nbytes > queue_cap:
+                refused += 1
+            else:
+                bx = synth.amr_boxes(mechs_[k], 1, 10_000 + i, max_cells=args.max_box_cells)[0]
+                rid = srv.submit(handles[k], bx.T, bx.Y, synth.P_ATM, bx.dt, 1e-8, 1e-12)
+                pending[rid] = (arrivals[i], bx.T.size, nbytes, k)
+                held += nbytes
+                accepted += 1
             i += 1
         for rid in list(pending):
             r = srv.poll(rid)
             if r is not None:
-                lat.append(r[2])
-                cells += pending.pop(rid)
-                if len(lat) % 50 == 0:
-                    print(f"serve: {len(lat)}/{len(reqs)} done, {len(pending)} pending, t={now:.1f}s",
-                          file=sys.stderr, flush=True)
+                ta, nc, nbytes, k = pending.pop(rid)
+                held -= nbytes
+                lt = (time.perf_counter() - t0 - ta) * 1e3
+                lat.append(lt)
+                lat_by[k].append(lt)
+                cells_done += nc
+        if now >= next_report:
+            print(f"serve: t={now:.0f}s offered {i} accepted {accepted} refused {refused} done {len(lat)} "
+                  f"pending {len(pending)} cells done {cells_done}", file=sys.stderr, flush=True)
+            next_report += 10.0
         time.sleep(0.0005)
     el = time.perf_counter() - t0
     st = srv.stats()
+    unfinished = len(pending)
+    print(f"serve: stopping after {el:.1f} s with {unfinished} requests unfinished", file=sys.stderr, flush=True)
     srv.close()
+
+    def q(v, p_):
+        return float(np.percentile(v, p_)) if v else None
     print(json.dumps({
-        "mode": "serve", "metric": METRIC, "value": cells / el, "unit": "cells/s", "n_gpus": 1,
+        "mode": "serve", "metric": METRIC, "value": cells_done / el, "unit": "cells/s", "n_gpus": 1,
         "dtype": "f64+f32lu" if args.lu_fp32 else "f64",
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "what": "request arrival to results on the host"},
-        "config": {"workload": f"Poisson {args.rate:g} req/s for {args.duration:g} s, mechanisms G(10,25,3,s1) | "
-                               f"G(53,325,4,s2) p=0.5, edges 8..64 capped at {args.max_box_cells} cells",
-                   "requests": len(reqs), "budget_gb": args.budget_gb},
+        "latency_ms": {"p50": q(lat, 50), "p99": q(lat, 99), "what": "trace arrival to results on the host, "
+                       "completed requests only"},
+        "latency_ms_by_mechanism": {"G(10,25,3)": {"n": len(lat_by[0]), "p50": q(lat_by[0], 50), "p99": q(lat_by[0], 99)},
+                                    "G(53,325,4)": {"n": len(lat_by[1]), "p50": q(lat_by[1], 50), "p99": q(lat_by[1], 99)}},
+        "requests": {"offered": int(i), "trace": int(arrivals.size), "accepted": accepted, "refused_at_door": refused,
+                     "completed": len(lat), "unfinished_at_stop": unfinished},
+        "config": {"workload": f"Poisson {args.rate:g} req/s over {args.duration:g} s, mechanisms G(10,25,3,s1) | "
+                               f"G(53,325,4,s2) p=0.5, edges log-uniform 8..64"
+                               + (f" capped at {args.max_box_cells} cells" if args.max_box_cells else "")
+                               + (", Newton matrix kept while recent" if args.jac_reuse else ""),
+                   "budget_gb": args.budget_gb, "queue_gb": args.queue_gb, "wall_s": args.wall},
         "server": st, "wall_s": el,
     }), flush=True)
 

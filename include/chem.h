@@ -97,6 +97,10 @@ typedef struct {
                                    get that state and status 0, counters include the retry work, and the
                                    stats are recomputed.  Keeps a device copy of the input state
                                    (16(S+1) bytes per cell); wall_ms times the first pass.  Default 0 */
+#define CHEM_OPT_PROGRESS 14    /* s > 0: while chem_integrate_boxes waits for per-box completion times
+                                   (box_ms given), it writes a line to stderr every s seconds with the
+                                   boxes and cells completed so far, read from the completion flags
+                                   (for long batches); default 0 (silent) */
 #define CHEM_OPT_JAC_REUSE 12   /* 1: keep the factored Newton matrix M = I - cJ across attempts while c
                                    is within 30% of the c it was formed with, fewer than 20 accepted
                                    steps have passed and Newton has not failed with it (a failure
@@ -206,50 +210,64 @@ int chem_autotune(chem_mech* m, int64_t n_cells, const double* T, const double* 
                   double atol, int* best_width, int* best_waves);
 
 /* ------------------------------------------------------------ serving ---
- * A continuous-batching request server.  Clients submit box-solve requests
- * (host arrays, any loaded mechanism, own dt/tolerances) at any time; a
- * dispatcher thread admits them in arrival order while their device memory
- * fits in the HBM budget, and launches everything admitted since the previous
- * launch as one batched launch per mechanism on one of `streams` streams, so
- * requests that arrive while others run overlap with them on the device.
- * Results come back to pinned host memory; latency is arrival (submit) to
+ * A continuous-batching request server (the serving extension of the
+ * batched solve, Sec. 5.1's many-small-boxes setting at request level).
+ * Clients submit box-solve requests (host arrays, any loaded mechanism, own
+ * dt) at any time.  A dispatcher thread admits them in arrival order while
+ * their state and per-cell records fit in the device arena (the HBM budget),
+ * copies them in, and appends their cells, in tiles, to the work queue of a
+ * resident kernel already running for the same mechanism, pressure and
+ * tolerances (a channel): its waves take the new tiles as they finish the
+ * ones they hold, so requests join work in flight instead of waiting for a
+ * launch.  A wave leaves after about 20 ms without work, or between tiles
+ * after 200 ms (so that channels share the GPU); the dispatcher relaunches a
+ * channel while it has work.  The last tile of a box raises a host-mapped
+ * flag; results then come back through pinned memory.  Latency is submit to
  * results on the host.  The handles passed to submit must stay alive, and
  * their options unchanged, until the server is drained. */
 typedef struct chem_server chem_server;
 
 typedef struct {
   int64_t submitted, completed, cells_completed;
-  int64_t launches;
+  int64_t launches;          /* resident-kernel launches */
   int64_t bytes_in_use, bytes_peak, budget_bytes;
   int64_t queued;            /* waiting for admission */
   int64_t in_flight;         /* admitted, not yet completed */
 } chem_server_stats;
 
-/* Create a server with an HBM budget for request state (bytes) and a number
- * of concurrent launch streams (1..8).  The budget is reserved as one device
- * arena at creation.  Errors: CHEM_ERR_ARG, CHEM_ERR_OOM, CHEM_ERR_DEVICE. */
+/* Create a server with an HBM budget (bytes) for request state and records
+ * (8 (S+1) + 36 bytes per cell) and a number of channels (1..8): resident
+ * kernels, each serving one (mechanism, pressure, tolerances) at a time.
+ * With fewer channels than such keys in the traffic, a channel drains and
+ * changes key.  The budget is reserved as one device arena at creation,
+ * with pinned staging of a quarter of it (at most 8 GiB).  Errors:
+ * CHEM_ERR_ARG, CHEM_ERR_OOM, CHEM_ERR_DEVICE. */
 int chem_server_create(int64_t budget_bytes, int streams, chem_server** out);
 
 /* Queue one request: n_cells cells of mechanism m with host arrays T[n] and
  * Y[S*n] (SoA, copied at submit), pressure p, step dt and tolerances.  *id
- * receives the request id.  A request larger than the whole budget is
- * rejected with CHEM_ERR_OOM. */
+ * receives the request id.  A request larger than the whole budget (or the
+ * staging area) is rejected with CHEM_ERR_OOM; after a device error every
+ * submit returns CHEM_ERR_DEVICE. */
 int chem_server_submit(chem_server* s, chem_mech* m, int64_t n_cells, const double* T, const double* Y, double p,
                        double dt, double rtol, double atol, int64_t* id);
 
 /* Non-blocking completion check.  Returns 1 and fills T_out/Y_out (host, may
- * be NULL), latency_ms and status (CHEM_OK or CHEM_WARN_CELLS_FAILED) when the
- * request is done (the request is then forgotten), 0 while pending, or an
- * error code for an unknown id. */
+ * be NULL), latency_ms and status when the request is done (the request is
+ * then forgotten), 0 while pending, or an error code for an unknown id.
+ * status: CHEM_OK, CHEM_WARN_CELLS_FAILED, the code of a refused kernel
+ * choice (e.g. CHEM_ERR_UNSUPPORTED), or CHEM_ERR_DEVICE; on an error the
+ * output arrays are left alone. */
 int chem_server_poll(chem_server* s, int64_t id, double* T_out, double* Y_out, double* latency_ms, int* status);
 
-/* Block until every submitted request has completed. */
+/* Block until every submitted request has completed (CHEM_ERR_DEVICE if
+ * the server met a device error). */
 int chem_server_drain(chem_server* s);
 
 int chem_server_stats_get(chem_server* s, chem_server_stats* out);
 
-/* Stop the dispatcher and release everything (pending requests are
- * dropped). */
+/* Stop the dispatcher and the resident kernels (each wave leaves after the
+ * tile it holds) and release everything; pending requests are dropped. */
 void chem_server_destroy(chem_server* s);
 
 /* Rates of one state per cell (Eq. 2-3, Eq. 7): wdot[S * n] (mol m^-3 s^-1,

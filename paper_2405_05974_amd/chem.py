@@ -40,6 +40,7 @@ OPT_JAC = 11             # 0 analytic, 1 difference quotients, 2 difference-quot
 JAC_ANALYTIC, JAC_FD, JAC_FD_T = 0, 1, 2
 OPT_RETRY = 13           # failed cells retried with dt split into 2, 4, ... 2^k substeps
 OPT_JAC_REUSE = 12       # 1: keep the factored Newton matrix while recent; 0 (default): fresh every attempt
+OPT_PROGRESS = 14        # s > 0: progress lines from chem_integrate_boxes every s seconds (per-box times on)
 
 EXPORTED = ("chem_mech_load", "chem_mech_load_str", "chem_mech_free", "chem_mech_info", "chem_set_stream",
             "chem_set_option", "chem_integrate", "chem_integrate_ex", "chem_integrate_noalloc", "chem_integrate_boxes",
@@ -194,11 +195,13 @@ class Mechanism:
         _check(self.lib, self.lib.chem_set_option(self.h, int(key), float(value)))
 
     def set_options(self, max_steps=None, q_max=None, fixed_T=None, fixed_step_n=None, lu_fp32=None, ir_max=None,
-                    graph=None, waves_per_cu=None, group_width=None, kernel=None, jac=None, jac_reuse=None, retry=None):
+                    graph=None, waves_per_cu=None, group_width=None, kernel=None, jac=None, jac_reuse=None, retry=None,
+                    progress=None):
         for key, val in ((OPT_MAX_STEPS, max_steps), (OPT_Q_MAX, q_max), (OPT_FIXED_T, fixed_T),
                          (OPT_FIXED_STEP, fixed_step_n), (OPT_LU_FP32, lu_fp32), (OPT_IR_MAX, ir_max),
                          (OPT_GRAPH, graph), (OPT_WAVES_PER_CU, waves_per_cu), (OPT_GROUP_WIDTH, group_width),
-                         (OPT_KERNEL, kernel), (OPT_JAC, jac), (OPT_JAC_REUSE, jac_reuse), (OPT_RETRY, retry)):
+                         (OPT_KERNEL, kernel), (OPT_JAC, jac), (OPT_JAC_REUSE, jac_reuse), (OPT_RETRY, retry),
+                         (OPT_PROGRESS, progress)):
             if val is not None:
                 self.set_option(key, float(val))
 

@@ -64,6 +64,7 @@ struct chem_mech {
   double* retry_in = nullptr;    // the call's input state [T | Y], kept for retries
   int64_t retry_cap = 0;
   int use_graph = 1, waves_per_cu = 8;
+  double progress_s = 0.0;       // seconds between progress lines of chem_integrate_boxes (0: none)
   int kernel_mode = 0;           // 0 auto, 1 group kernels, 2 lane-per-cell kernels
   // lane-per-cell module (generated source, compiled on first use per device)
   std::mutex lpc_mu;
@@ -71,6 +72,7 @@ struct chem_mech {
   void* lpc_integrate = nullptr;
   void* lpc_boxes = nullptr;
   void* lpc_rates = nullptr;
+  void* lpc_serve = nullptr;
   int lpc_device = -1;
   int lpc_reuse = -1;   // CH_REUSE of the loaded module
   // workspace
@@ -96,7 +98,7 @@ struct chem_mech {
 namespace chemgpu {
 std::string lpc_source(const HostMech& m, bool reuse);
 int lpc_module(const std::string& src, int device, void** integrate_fn, void** boxes_fn, void** rates_fn,
-               std::string& log);
+               void** serve_fn, std::string& log);
 }  // namespace chemgpu
 
 // Kernel family for the next integration with this handle's options: sets

@@ -15,6 +15,7 @@
 #include <new>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "chem_handle.h"
@@ -493,7 +494,8 @@ int chem_select_kernel(chem_mech* m, bool* lpc) {
   if (lpc_ready(m)) return CHEM_OK;
   if (m->lpc_src.empty() || m->lpc_reuse != reuse) m->lpc_src = chemgpu::lpc_source(m->host, reuse != 0);
   std::string log;
-  if (chemgpu::lpc_module(m->lpc_src, m->device, &m->lpc_integrate, &m->lpc_boxes, &m->lpc_rates, log) != 0)
+  if (chemgpu::lpc_module(m->lpc_src, m->device, &m->lpc_integrate, &m->lpc_boxes, &m->lpc_rates, &m->lpc_serve,
+                          log) != 0)
     return fail(CHEM_ERR_DEVICE, log);
   m->lpc_device = m->device;
   m->lpc_reuse = reuse;
@@ -623,6 +625,10 @@ int chem_set_option(chem_mech* m, int key, double value) {
       m->dev.nch = m->nch_np[wi];
       return CHEM_OK;
     }
+    case CHEM_OPT_PROGRESS:
+      if (!(value >= 0) || !std::isfinite(value)) return fail(CHEM_ERR_ARG, "progress interval must be >= 0");
+      m->progress_s = value;
+      return CHEM_OK;
     default:
       return fail(CHEM_ERR_ARG, "unknown option key " + std::to_string(key));
   }
@@ -1068,15 +1074,26 @@ int chem_integrate_boxes(chem_mech* m, int n_boxes, const chem_box* boxes, doubl
     if (box_ms) {
       std::vector<char> seen(n_boxes, 0);
       int left = n_boxes;
+      int64_t cells_done = 0;
+      double next_report = m->progress_s * 1e3;
       volatile int* flags = m->host_done;
       while (left > 0) {
         for (int b = 0; b < n_boxes; ++b) {
           if (!seen[b] && flags[b]) {
             seen[b] = 1;
             --left;
+            cells_done += boxes[b].n_cells;
             box_ms[b] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
           }
         }
+        const double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (m->progress_s > 0 && el >= next_report) {
+          std::fprintf(stderr, "chem_integrate_boxes: %d of %d boxes, %lld of %lld cells done after %.1f s\n",
+                       n_boxes - left, n_boxes, (long long)cells_done, (long long)cells, el * 1e-3);
+          std::fflush(stderr);
+          next_report += m->progress_s * 1e3;
+        }
+        if (left > 0) std::this_thread::sleep_for(std::chrono::microseconds(50));
         if (left > 0 && hipStreamQuery(m->stream) != hipErrorNotReady) {
           // the stream is done (or failed): every remaining box is complete
           const double now = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

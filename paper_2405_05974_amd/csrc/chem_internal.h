@@ -75,6 +75,41 @@ struct BoxJob {
   int64_t total_cells;
 };
 
+// One box of a resident serving kernel: a request's cells (or a part of
+// them), with its own state and records in device memory.
+struct ServeBox {
+  double* T;           // [n]
+  double* Y;           // [S * n], SoA within the box
+  int32_t* rec;        // [kRecRows * n], rows n apart
+  int64_t n;           // cells
+  double dt;           // flow step of this box, s
+  int64_t tile_pre;    // first tile of this box (set when it is published)
+};
+
+// Work queue of a resident serving kernel (continuous batching); the host
+// half of the protocol, and the protocol itself, are in chem_serve_ring.h.
+// The host appends boxes while the kernel runs: box descriptors in ring
+// slots, the slot of every published tile in tile_slot, the published tile
+// count in pub (all host-mapped, coherent).  Lane 0 of a wave claims a tile
+// below *pub by compare-and-swap on head (device memory) and reads only its
+// own box; the wave that finishes a box's last tile resets the slot's
+// finished counter and sets done[slot] (host-mapped).  A wave leaves after
+// idle_polls empty polls, at the stop flag, or between tiles once it has
+// run for `quantum` ticks of the 100 MHz real-time counter (0: never), so
+// every launch ends and the host relaunches while boxes are live.
+struct ServeQueue {
+  const ServeBox* boxes;       // host-mapped [ring slots]
+  const unsigned* tile_slot;   // host-mapped [tile_mask + 1]
+  const unsigned* pub;         // host-mapped: tiles published
+  const int* stop;             // host-mapped
+  unsigned* head;              // device: next tile to claim
+  int* finished;               // device [ring slots]: tiles finished of the slot's box
+  int* done;                   // host-mapped [ring slots]
+  unsigned tile_mask;
+  int idle_polls;
+  int64_t quantum;
+};
+
 struct IntParams {
   double p, dt, rtol, atol;
   int max_steps, q_max, fixed_T, fixed_step_n;
@@ -97,6 +132,15 @@ hipError_t launch_reduce_records_job(const int32_t* rec, const BoxJob* job, unsi
 size_t integrate_lds_bytes(int np_width, int N, bool f32);
 hipError_t launch_boxes_init(const BoxDev* boxes, const BoxJob* job, unsigned* head, int* remaining,
                              hipStream_t stream);
+// Resident serving kernel of the group family on `grid` waves, and the
+// waves of it one CU can hold (occupancy).
+hipError_t launch_serve(const DevMech& m, const IntParams& prm, const ServeQueue& q, int grid, hipStream_t stream);
+int serve_waves_per_cu(const DevMech& m, bool f32);
+// Zero `count` unsigned words of device memory with a kernel (no memset node).
+hipError_t launch_zero_u32(unsigned* p, int count, hipStream_t stream);
+// Copy `count` 32-bit words with a kernel (device or host-mapped memory on
+// either side); ordinary stores, so a later kernel on the device sees them.
+hipError_t launch_copy_words(uint32_t* dst, const uint32_t* src, int64_t count, hipStream_t stream);
 
 // Lane-per-cell kernels, generated per mechanism and compiled with hipRTC
 // (chem_jit.cpp).  Largest state size N = S + 1 they serve.
@@ -107,5 +151,7 @@ hipError_t launch_lpc_rates(void* fn, double p, int fixed_T, const double* T, co
                             double* wdot, double* f, double* jac, hipStream_t stream);
 hipError_t launch_lpc_boxes(void* fn, const IntParams& prm, const BoxDev* boxes, const BoxJob* job, unsigned* head,
                             int* remaining, int32_t* rec, int* host_done, int grid, hipStream_t stream);
+hipError_t launch_lpc_serve(void* fn, const IntParams& prm, const ServeQueue& q, int grid, hipStream_t stream);
+int lpc_serve_waves_per_cu(void* fn);
 
 }  // namespace chemgpu

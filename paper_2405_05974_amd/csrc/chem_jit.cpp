@@ -600,6 +600,7 @@ struct LpcModule {
   hipFunction_t integrate = nullptr;
   hipFunction_t boxes = nullptr;
   hipFunction_t rates = nullptr;
+  hipFunction_t serve = nullptr;
 };
 
 std::mutex g_jit_mu;
@@ -609,7 +610,7 @@ std::map<std::pair<int, std::string>, LpcModule> g_jit_cache;   // (device, sour
 
 // Compile (or fetch) the lane-per-cell module of `src` for the current device.
 int lpc_module(const std::string& src, int device, void** integrate_fn, void** boxes_fn, void** rates_fn,
-               std::string& log) {
+               void** serve_fn, std::string& log) {
   std::lock_guard<std::mutex> lk(g_jit_mu);
   auto key = std::make_pair(device, src);
   auto it = g_jit_cache.find(key);
@@ -617,6 +618,7 @@ int lpc_module(const std::string& src, int device, void** integrate_fn, void** b
     *integrate_fn = it->second.integrate;
     *boxes_fn = it->second.boxes;
     *rates_fn = it->second.rates;
+    *serve_fn = it->second.serve;
     return 0;
   }
   hipDeviceProp_t prop;
@@ -655,7 +657,8 @@ int lpc_module(const std::string& src, int device, void** integrate_fn, void** b
   if (hipModuleLoadData(&mod.mod, code.data()) != hipSuccess ||
       hipModuleGetFunction(&mod.integrate, mod.mod, "chem_lpc_integrate") != hipSuccess ||
       hipModuleGetFunction(&mod.boxes, mod.mod, "chem_lpc_boxes") != hipSuccess ||
-      hipModuleGetFunction(&mod.rates, mod.mod, "chem_lpc_rates") != hipSuccess) {
+      hipModuleGetFunction(&mod.rates, mod.mod, "chem_lpc_rates") != hipSuccess ||
+      hipModuleGetFunction(&mod.serve, mod.mod, "chem_lpc_serve") != hipSuccess) {
     log = "loading the lane-per-cell module failed";
     return -1;
   }
@@ -663,6 +666,7 @@ int lpc_module(const std::string& src, int device, void** integrate_fn, void** b
   *integrate_fn = mod.integrate;
   *boxes_fn = mod.boxes;
   *rates_fn = mod.rates;
+  *serve_fn = mod.serve;
   return 0;
 }
 
@@ -711,6 +715,36 @@ hipError_t launch_lpc_boxes(void* fn, const IntParams& prm, const BoxDev* boxes,
                             int* remaining, int32_t* rec, int* host_done, int grid, hipStream_t stream) {
   LpcParams q = lpc_params(prm);
   void* args[] = {&q, &boxes, &job, &head, &remaining, &rec, &host_done};
+  return hipModuleLaunchKernel((hipFunction_t)fn, (unsigned)grid, 1, 1, 64, 1, 1, 0, stream, args, nullptr);
+}
+
+namespace {
+struct LpcServeQ {   // layout of ChServeQ in the generated source
+  const ServeBox* boxes;
+  const unsigned* tile_slot;
+  const unsigned* pub;
+  const int* stop;
+  unsigned* head;
+  int* finished;
+  int* done;
+  unsigned tile_mask;
+  int idle_polls;
+  long long quantum;
+};
+static_assert(sizeof(ServeBox) == 48, "ChServeBox mirrors ServeBox");
+}  // namespace
+
+int lpc_serve_waves_per_cu(void* fn) {
+  int blocks = 0;
+  const hipError_t e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (hipFunction_t)fn, 64, 0);
+  return e == hipSuccess && blocks > 0 ? blocks : 1;
+}
+
+hipError_t launch_lpc_serve(void* fn, const IntParams& prm, const ServeQueue& q, int grid, hipStream_t stream) {
+  LpcParams pq = lpc_params(prm);
+  LpcServeQ sq{q.boxes, q.tile_slot, q.pub, q.stop, q.head, q.finished, q.done, q.tile_mask, q.idle_polls,
+               (long long)q.quantum};
+  void* args[] = {&pq, &sq};
   return hipModuleLaunchKernel((hipFunction_t)fn, (unsigned)grid, 1, 1, 64, 1, 1, 0, stream, args, nullptr);
 }
 

@@ -15,6 +15,7 @@
 // same expression on the same operands, so group decisions never split.
 #include "chem_internal.h"
 
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -1147,6 +1148,118 @@ __global__ __launch_bounds__(kWave) void boxes_kernel(const DevMech m, const Int
   }
 }
 
+// Resident serving kernel: the box loop of boxes_kernel over a queue the
+// host appends to while it runs (see ServeQueue).  Lane 0 claims a tile by
+// compare-and-swap below the published count, polling with s_sleep while
+// none is published, for at most q.idle_spins empty polls or until q.stop.
+// Device half of the serving queue protocol (the queue layout is described
+// with ServeQueue).  serve_claim runs on lane 0 only: it returns 1 with the
+// claimed tile and its ring slot, or 0 when the wave should leave.  The
+// published count is polled with relaxed loads and backoff; the acquire
+// fence after a successful claim pairs with the host's release of *pub.
+__device__ int serve_claim(const ServeQueue& q, unsigned* item, unsigned* slot) {
+  unsigned backoff = 1;
+  int polls = 0;
+  for (int tries = 0; tries < (1 << 22); ++tries) {
+    if (__hip_atomic_load(q.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) return 0;
+    const unsigned pub = __hip_atomic_load(q.pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    unsigned h = __hip_atomic_load(q.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (h < pub) {
+      if (__hip_atomic_compare_exchange_strong(q.head, &h, h + 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT)) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+        *item = h;
+        *slot = __hip_atomic_load(&q.tile_slot[h & q.tile_mask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        return 1;
+      }
+      continue;   // another wave took tile h: look again at once
+    }
+    if (++polls >= q.idle_polls) return 0;
+    for (unsigned z = 0; z < backoff; ++z) __builtin_amdgcn_s_sleep(127);
+    if (backoff < 16) backoff <<= 1;
+  }
+  return 0;
+}
+
+// Lane 0, after the wave's stores of the tile: count the tile, and on the
+// box's last one reset the counter for the slot's next box and raise done.
+__device__ void serve_finish(const ServeQueue& q, unsigned slot, int tiles) {
+  const int fin = __hip_atomic_fetch_add(&q.finished[slot], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
+  if (fin == tiles) {
+    __hip_atomic_store(&q.finished[slot], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&q.done[slot], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+// A box descriptor read by lane 0 from host-mapped memory (atomic loads, so
+// that no cached copy of an earlier box in the slot is used) and broadcast.
+struct ServeBoxRegs {
+  double* T;
+  double* Y;
+  int32_t* rec;
+  int64_t n, tile_pre;
+  double dt;
+};
+
+__device__ __forceinline__ uint64_t bcast_u64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t load_sys_u64(const void* p) {
+  return __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+template <int NP, bool F32>
+__global__ __launch_bounds__(kWave) void serve_kernel(const DevMech m, const IntParams P, const ServeQueue q) {
+  extern __shared__ double smem[];
+  const Shared sh = carve(smem, NP, m.N, F32);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int r = lane % NP;
+  const int g = lane / NP;
+  constexpr int kCpt = kWave / NP;
+  init_shared_constants<NP>(m, sh);
+  const Spc sc = load_species(m, r);
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  for (;;) {
+    unsigned item = 0, slot = 0;
+    int got = 0;
+    uint64_t w[6] = {0, 0, 0, 0, 0, 0};
+    if (lane == 0) {
+      got = serve_claim(q, &item, &slot);
+      if (got) {
+        const uint64_t* d = reinterpret_cast<const uint64_t*>(&q.boxes[slot]);
+        for (int i = 0; i < 6; ++i) w[i] = load_sys_u64(d + i);
+      }
+    }
+    if (!__builtin_amdgcn_readfirstlane(got)) break;
+    item = (unsigned)__builtin_amdgcn_readfirstlane((int)item);
+    slot = (unsigned)__builtin_amdgcn_readfirstlane((int)slot);
+    ServeBoxRegs bx;
+    bx.T = reinterpret_cast<double*>(bcast_u64(w[0]));
+    bx.Y = reinterpret_cast<double*>(bcast_u64(w[1]));
+    bx.rec = reinterpret_cast<int32_t*>(bcast_u64(w[2]));
+    bx.n = (int64_t)bcast_u64(w[3]);
+    bx.dt = __builtin_bit_cast(double, bcast_u64(w[4]));
+    bx.tile_pre = (int64_t)bcast_u64(w[5]);
+    const int64_t c = ((int64_t)item - bx.tile_pre) * kCpt + g;
+    if (c < bx.n) integrate_group<NP, F32>(m, P, bx.dt, sh, sc, bx.T, bx.Y, bx.n, c, bx.rec, bx.n, c);
+    __syncthreads();
+    if (lane == 0) serve_finish(q, slot, (int)((bx.n + kCpt - 1) / kCpt));
+    if (q.quantum > 0 && (int64_t)(__builtin_amdgcn_s_memrealtime() - t0) > q.quantum) break;
+  }
+}
+
+__global__ void zero_u32_kernel(unsigned* __restrict__ p, const int count) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+__global__ void copy_words_kernel(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src, const int64_t count) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) dst[i] = src[i];
+}
+
 // Queue counters for boxes_kernel: head = 0, remaining[i] = tiles of box i.
 __global__ void boxes_init_kernel(const BoxDev* __restrict__ boxes, const BoxJob* __restrict__ job,
                                   unsigned* __restrict__ head, int* __restrict__ remaining) {
@@ -1281,7 +1394,59 @@ hipError_t launch_boxes_np(const DevMech& m, const IntParams& prm, const BoxDev*
   return hipGetLastError();
 }
 
+template <int NP>
+hipError_t launch_serve_np(const DevMech& m, const IntParams& prm, const ServeQueue& q, int grid, hipStream_t stream) {
+  const bool f32 = prm.lu_fp32 != 0;
+  const size_t lds = integrate_lds_bytes(NP, m.N, f32);
+  if (f32)
+    hipLaunchKernelGGL((serve_kernel<NP, true>), dim3(grid), dim3(kWave), lds, stream, m, prm, q);
+  else
+    hipLaunchKernelGGL((serve_kernel<NP, false>), dim3(grid), dim3(kWave), lds, stream, m, prm, q);
+  return hipGetLastError();
+}
+
+template <int NP>
+int serve_waves_np(const DevMech& m, bool f32) {
+  int blocks = 0;
+  const size_t lds = integrate_lds_bytes(NP, m.N, f32);
+  const hipError_t e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, serve_kernel<NP, true>, kWave, lds)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, serve_kernel<NP, false>, kWave, lds);
+  return e == hipSuccess && blocks > 0 ? blocks : 1;
+}
+
 }  // namespace
+
+hipError_t launch_serve(const DevMech& m, const IntParams& prm, const ServeQueue& q, int grid, hipStream_t stream) {
+  switch (m.np_width) {
+    case 16: return launch_serve_np<16>(m, prm, q, grid, stream);
+    case 32: return launch_serve_np<32>(m, prm, q, grid, stream);
+    case 64: return launch_serve_np<64>(m, prm, q, grid, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int serve_waves_per_cu(const DevMech& m, bool f32) {
+  switch (m.np_width) {
+    case 16: return serve_waves_np<16>(m, f32);
+    case 32: return serve_waves_np<32>(m, f32);
+    case 64: return serve_waves_np<64>(m, f32);
+    default: return 1;
+  }
+}
+
+hipError_t launch_zero_u32(unsigned* p, int count, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_u32_kernel, dim3((count + 255) / 256 < 64 ? (count + 255) / 256 : 64), dim3(256), 0, stream,
+                     p, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_words(uint32_t* dst, const uint32_t* src, int64_t count, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((count + 1023) / 1024, 4096);
+  hipLaunchKernelGGL(copy_words_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, dst, src, count);
+  return hipGetLastError();
+}
 
 hipError_t launch_boxes_init(const BoxDev* boxes, const BoxJob* job, unsigned* head, int* remaining,
                              hipStream_t stream) {

@@ -713,7 +713,12 @@ def test_fp32_lu_with_kept_matrices(chem, torch_dev):
 
 # ------------------------------------------------------------------ serving
 
-def test_server_results_same_alone_and_in_the_mix(chem, torch_dev):
+@pytest.mark.parametrize("streams", [1, 3])
+def test_server_results_same_alone_and_in_the_mix(chem, torch_dev, streams):
+    """Two mechanisms (lane-per-cell and group kernels) through the resident
+    serving kernels: with one channel the channel drains and changes
+    mechanism, with three each mechanism keeps its own.  Every served result
+    equals the GPU's lone run bit for bit and the oracle at the FP64 bar."""
     import time
     mechs_ = [synth.config_mechanism(2), synth.config_mechanism(4)]
     texts = [m.to_text() for m in mechs_]
@@ -725,8 +730,8 @@ def test_server_results_same_alone_and_in_the_mix(chem, torch_dev):
         reqs.append((k, bx))
     S_max = max(m.n_species for m in mechs_)
     budget = 3 * 8 * (S_max + 1) * 48           # about three requests resident at once
-    say(f"server: {len(reqs)} requests, budget {budget} B")
-    srv = chem.Server(budget, streams=3)
+    say(f"server: {len(reqs)} requests, budget {budget} B, {streams} channel(s)")
+    srv = chem.Server(budget, streams=streams)
     ids = []
     for k, bx in reqs:
         ids.append(srv.submit(handles[k], bx.T, bx.Y, synth.P_ATM, bx.dt, 1e-8, 1e-12))
@@ -755,10 +760,56 @@ def test_server_results_same_alone_and_in_the_mix(chem, torch_dev):
         assert_parity(T, Y, To, Yo, f"served request {i}")
 
 
+def test_server_appends_to_a_running_kernel(chem, torch_dev):
+    """Requests submitted while the resident kernel works on an earlier,
+    larger one join its queue instead of waiting for a launch of their own:
+    fewer launches than requests.  Every small request against the oracle at
+    the FP64 bar, the large one against the GPU's lone run (bit for bit) and
+    on a sample of its cells against the oracle."""
+    import time
+    m = synth.config_mechanism(1)
+    text = m.to_text()
+    h = chem.Mechanism(text)
+    big = synth.uniform_batch(m, 16384, 71, 1000.0, 1600.0, 1e-5, 1e-8, 1e-12)
+    small = [synth.uniform_batch(m, 29 + 23 * i, 80 + i, 1000.0, 1600.0, 2e-6 * (i + 1), 1e-8, 1e-12)
+             for i in range(8)]
+    say("server: one 16384-cell request, then 8 small ones while it runs")
+    srv = chem.Server(1 << 28, streams=1)
+    ids = [srv.submit(h, big.T, big.Y, big.p, big.dt, big.rtol, big.atol)]
+    for w in small:
+        ids.append(srv.submit(h, w.T, w.Y, w.p, w.dt, w.rtol, w.atol))
+    out = {}
+    t_end = time.time() + 120
+    while len(out) < len(ids) and time.time() < t_end:
+        for rid in ids:
+            if rid not in out:
+                r = srv.poll(rid)
+                if r is not None:
+                    out[rid] = r
+        time.sleep(0.001)
+    st = srv.stats()
+    srv.close()
+    say(f"server stats {st}")
+    assert len(out) == len(ids) and st["completed"] == len(ids)
+    assert st["launches"] < len(ids)
+    T, Y, lat, status = out[ids[0]]
+    assert status == 0
+    Tg, Yg, _, _ = gpu_integrate(chem, torch_dev, text, big.T, big.Y, big.p, big.dt, big.rtol, big.atol)
+    assert np.array_equal(T, Tg) and np.array_equal(Y, Yg)
+    pick = np.random.default_rng(5).choice(big.T.size, 64, replace=False)
+    To, Yo, _ = oracle_integrate(text, big.T[pick], big.Y[:, pick], big.p, big.dt, big.rtol, big.atol)
+    assert_parity(T[pick], Y[:, pick], To, Yo, "served large request, sampled cells")
+    for i, (rid, w) in enumerate(zip(ids[1:], small)):
+        T, Y, lat, status = out[rid]
+        assert status == 0
+        To, Yo, _ = oracle_integrate(text, w.T, w.Y, w.p, w.dt, w.rtol, w.atol)
+        assert_parity(T, Y, To, Yo, f"served small request {i}")
+
+
 def test_server_failed_request_polls_cleanly(chem, torch_dev):
-    """A request whose launch the host refuses (the lane-per-cell family asked
+    """A request whose kernel the host refuses (the lane-per-cell family asked
     for a 30-species mechanism, beyond its size: nothing reaches the GPU)
-    completes with an error status; polling it returns that status and leaves
+    completes with that refusal's status (CHEM_ERR_UNSUPPORTED); polling it returns that status and leaves
     the caller's output arrays untouched, and the server keeps serving."""
     import time
     m = synth.config_mechanism(4)
@@ -776,7 +827,7 @@ def test_server_failed_request_polls_cleanly(chem, torch_dev):
         time.sleep(0.001)
     assert r is not None
     T, Y, lat, status = r
-    assert status == chem.CHEM_ERR_DEVICE and np.isnan(T).all() and np.isnan(Y).all()
+    assert status == chem.CHEM_ERR_UNSUPPORTED and np.isnan(T).all() and np.isnan(Y).all()
     rid = srv.submit(good, bx.T, bx.Y, synth.P_ATM, bx.dt, 1e-8, 1e-12)
     srv.drain()
     T, Y, lat, status = srv.poll(rid)
