@@ -105,6 +105,7 @@ def main():
     ap.add_argument("--queue-gb", type=float, default=8.0,
                     help="serve: request state the host keeps waiting for the server; more is refused")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget")
+    ap.add_argument("--mix", type=float, default=0.5, help="serve: probability that a request is G(53,325,4)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (cells are independent, so "
@@ -612,7 +613,7 @@ def bench_sweep(args, torch, dev, chem, synth):
 def bench_serve(args, torch, dev, chem, synth):
     """The serving workload: Poisson arrivals at --rate req/s over --duration s
     of box-solve requests, each drawing G(10,25,3,s1) or G(53,325,4,s2) with
-    p = 0.5 and a cubic box of edge log-uniform in 8..64 cells (capped at
+    p = --mix (0.5) and a cubic box of edge log-uniform in 8..64 cells (capped at
     --max-box-cells when given), T, Y and dt as in the uneven-box workload,
     served under an HBM budget of --budget-gb.  A request's cells are drawn
     when it arrives.  The host keeps at most --queue-gb of request state
@@ -623,14 +624,18 @@ def bench_serve(args, torch, dev, chem, synth):
     mechs_ = [synth.config_mechanism(2), synth.config_mechanism(3)]
     handles = [chem.Mechanism(m.to_text()) for m in mechs_]
     for h in handles:
-        h.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32), jac_reuse=int(args.jac_reuse),
-                      kernel=KERNEL_CODES[args.kernel] if h.N <= LANE_MAX_N or args.kernel != "lane" else 0)
+        # FP32 LU where a kernel family has it: the group kernels of G(53,325,4); G(10,25,3)
+        # stays on the lane-per-cell kernels, which keep the whole 11x11 matrix in FP64 registers
+        lane = h.N <= LANE_MAX_N
+        h.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32 and not lane), jac_reuse=int(args.jac_reuse),
+                      kernel=KERNEL_CODES[args.kernel] if lane or args.kernel != "lane" else 0)
     arrivals = synth.poisson_trace(1005, args.rate, args.duration)
-    pick = np.random.default_rng(1005).integers(0, 2, size=arrivals.size)
+    pick = (np.random.default_rng(1005).random(arrivals.size) < args.mix).astype(int)
     srv = chem.Server(int(args.budget_gb * (1 << 30)), streams=4)
     queue_cap = args.queue_gb * (1 << 30)
     pending = {}                  # id -> (arrival s, cells, bytes)
     lat, lat_by = [], {0: [], 1: []}
+    cells_by = {0: 0, 1: 0}
     cells_done = accepted = refused = 0
     held = 0.0
     t0 = time.perf_counter()
@@ -666,6 +671,7 @@ def bench_serve(args, torch, dev, chem, synth):
                 lat.append(lt)
                 lat_by[k].append(lt)
                 cells_done += nc
+                cells_by[k] += nc
         if now >= next_report:
             print(f"serve: t={now:.0f}s offered {i} accepted {accepted} refused {refused} done {len(lat)} "
                   f"pending {len(pending)} cells done {cells_done}", file=sys.stderr, flush=True)
@@ -675,7 +681,6 @@ def bench_serve(args, torch, dev, chem, synth):
     st = srv.stats()
     unfinished = len(pending)
     print(f"serve: stopping after {el:.1f} s with {unfinished} requests unfinished", file=sys.stderr, flush=True)
-    srv.close()
 
     def q(v, p_):
         return float(np.percentile(v, p_)) if v else None
@@ -684,17 +689,22 @@ def bench_serve(args, torch, dev, chem, synth):
         "dtype": "f64+f32lu" if args.lu_fp32 else "f64",
         "latency_ms": {"p50": q(lat, 50), "p99": q(lat, 99), "what": "trace arrival to results on the host, "
                        "completed requests only"},
-        "latency_ms_by_mechanism": {"G(10,25,3)": {"n": len(lat_by[0]), "p50": q(lat_by[0], 50), "p99": q(lat_by[0], 99)},
-                                    "G(53,325,4)": {"n": len(lat_by[1]), "p50": q(lat_by[1], 50), "p99": q(lat_by[1], 99)}},
+        "latency_ms_by_mechanism": {"G(10,25,3)": {"n": len(lat_by[0]), "p50": q(lat_by[0], 50), "p99": q(lat_by[0], 99),
+                                                   "cells": cells_by[0]},
+                                    "G(53,325,4)": {"n": len(lat_by[1]), "p50": q(lat_by[1], 50), "p99": q(lat_by[1], 99),
+                                                    "cells": cells_by[1]}},
         "requests": {"offered": int(i), "trace": int(arrivals.size), "accepted": accepted, "refused_at_door": refused,
                      "completed": len(lat), "unfinished_at_stop": unfinished},
         "config": {"workload": f"Poisson {args.rate:g} req/s over {args.duration:g} s, mechanisms G(10,25,3,s1) | "
-                               f"G(53,325,4,s2) p=0.5, edges log-uniform 8..64"
+                               f"G(53,325,4,s2) p={args.mix:g}, edges log-uniform 8..64"
+                               + (", FP32 LU on G(53,325,4) (G(10,25,3) on the FP64 lane-per-cell kernels)"
+                                  if args.lu_fp32 else "")
                                + (f" capped at {args.max_box_cells} cells" if args.max_box_cells else "")
                                + (", Newton matrix kept while recent" if args.jac_reuse else ""),
                    "budget_gb": args.budget_gb, "queue_gb": args.queue_gb, "wall_s": args.wall},
         "server": st, "wall_s": el,
     }), flush=True)
+    srv.close()   # after the report: closing waits for the tiles the GPU holds
 
 
 if __name__ == "__main__":
