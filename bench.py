@@ -241,10 +241,12 @@ def main():
             "timing": "kernel_ms = median of the timed launches (HIP events on the launch stream)",
         },
     }
+    worst = None
     if args.lu_fp32:
         out["accuracy_vs_fp64_gpu"] = fp64_comparison(gm, T0, Y0, T, Y, w, torch)
+        worst = out["accuracy_vs_fp64_gpu"].pop("_worst")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"], out["accuracy"] = cpu_baseline(w, T, Y, args)
+        out["cpu_baseline"], out["accuracy"] = cpu_baseline(w, T, Y, args, worst)
     print(json.dumps(out), flush=True)
 
 
@@ -262,9 +264,17 @@ def fp64_comparison(gm, T0, Y0, T, Y, w, torch):
     dY = (Y - Y6).abs().amax(dim=0)
     dT = ((T - T6).abs() / T6)
     q = lambda t: float(torch.quantile(t.float().cpu(), 0.99))
+    err = torch.maximum(dY, dT)
+    over = int((err > 1e-6).sum())
+    worst = torch.topk(err, min(8, err.numel())).indices
+    wi = worst.cpu().numpy()
     return {"vs": "plain FP64 GPU path, same inputs and settings, every cell", "cells": int(T.numel()),
             "max_abs_dY": float(dY.max()), "p99_abs_dY": q(dY), "max_rel_dT": float(dT.max()), "p99_rel_dT": q(dT),
-            "fp64_kernel_ms": st["wall_ms"]}
+            "cells_over_1e-6": over, "fraction_over_1e-6": over / T.numel(),
+            "worst_cells": [{"cell": int(i), "T0": float(T0[i]), "rel_dT": float(dT[i]), "abs_dY": float(dY[i])}
+                            for i in wi],
+            "fp64_kernel_ms": st["wall_ms"],
+            "_worst": (wi, T6[worst].cpu().numpy(), Y6[:, worst].cpu().numpy())}
 
 
 def measured_profile(kernel):
@@ -296,10 +306,13 @@ def kernel_name(args, N):
     return f"integrate_kernel<{np_}, {'true' if args.lu_fp32 else 'false'}>"
 
 
-def cpu_baseline(w, Tg, Yg, args):
+def cpu_baseline(w, Tg, Yg, args, worst=None):
     """The oracle, built for this host (-march=native), on a strided sample of
     the same box with all host threads: the median of three timed runs; the
-    results also give the accuracy figures."""
+    results also give the accuracy figures.  `worst` = (cells, FP64 GPU T, Y
+    there) for the FP32-LU run: those cells also go through the oracle at the
+    same settings and at the tight tolerance, so that the FP32-LU and FP64
+    results there are both measured against the oracle and the truth."""
     import tempfile
     import oracle
     n = w.n_cells
@@ -356,6 +369,24 @@ def cpu_baseline(w, Tg, Yg, args):
                            "max_abs_dY_oracle": float(np.abs(Yo[:, pos] - Yt).max()),
                            "max_rel_dT_oracle": float((np.abs(To[pos] - Tt) / Tt).max()),
                            "what": "truth = the oracle at rtol 1e-12, atol 1e-20"}
+    if worst is not None:
+        wi, T6w, Y6w = worst
+        print(f"cpu baseline: oracle and truth on the {wi.size} cells where FP32 LU and FP64 differ most",
+              file=sys.stderr, flush=True)
+        Tow, Yow, _ = om.integrate(w.T[wi], w.Y[:, wi], w.p, w.dt, w.rtol, w.atol, q_max=args.q_max,
+                                   nthreads=threads, want_stats=False)
+        Ttw, Ytw, _ = om.integrate(w.T[wi], w.Y[:, wi], w.p, w.dt, 1e-12, 1e-20, q_max=args.q_max,
+                                   nthreads=threads, want_stats=False)
+        Tgw, Ygw = Tg.cpu().numpy()[wi], Yg.cpu().numpy()[:, wi]
+
+        def e(Ta, Ya, Tb, Yb):
+            return {"max_abs_dY": float(np.abs(Ya - Yb).max()), "max_rel_dT": float((np.abs(Ta - Tb) / Tb).max())}
+        acc["worst_fp32_cells"] = {
+            "cells": [int(i) for i in wi],
+            "fp32lu_vs_oracle": e(Tgw, Ygw, Tow, Yow), "fp64_gpu_vs_oracle": e(T6w, Y6w, Tow, Yow),
+            "fp32lu_vs_truth": e(Tgw, Ygw, Ttw, Ytw), "fp64_gpu_vs_truth": e(T6w, Y6w, Ttw, Ytw),
+            "oracle_vs_truth": e(Tow, Yow, Ttw, Ytw),
+            "what": "oracle = same settings (FP64 LU); truth = the oracle at rtol 1e-12, atol 1e-20"}
     # one core on a sub-sample of about 4 s
     n1 = int(max(1, min(idx.size, 4.0 * idx.size / (el * threads))))
     sub1 = idx[:: max(1, idx.size // n1)]

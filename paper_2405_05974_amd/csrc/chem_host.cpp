@@ -268,6 +268,29 @@ int upload(chem_mech* h) {
     for (int i = 0; i < d.nr; ++i) d.sp[i] = x.reac[i];
     for (int i = 0; i < d.np; ++i) d.sp[chemgpu::kMaxSide + i] = x.prod[i];
   }
+  // the hot fields again, one array per field
+  std::vector<double> rlnA(std::max(R, 1), 0.0), rb(std::max(R, 1), 0.0), rEaR(std::max(R, 1), 0.0);
+  std::vector<int4> rmeta(std::max(R, 1));
+  for (int j = 0; j < std::max(R, 1); ++j) rmeta[j] = int4{0, 0xFFFFFF, 0xFFFFFF, 0};
+  for (int j = 0; j < R; ++j) {
+    const RxParams& d = rx[j];
+    if (d.eff_off >= (1 << 20) || d.eff_n >= (1 << 11))
+      return fail(CHEM_ERR_UNSUPPORTED, "too many collision efficiencies");
+    rlnA[j] = d.lnA;
+    rb[j] = d.b;
+    rEaR[j] = d.EaR;
+    int4 mt;
+    mt.x = d.type | (d.rev << 2) | (d.nr << 3) | (d.np << 5) | ((d.ntroe > 0) << 7);
+    mt.y = 0;
+    mt.z = 0;
+    for (int s2 = 0; s2 < chemgpu::kSlots; ++s2) {
+      const int v = d.sp[s2] < 0 ? 255 : d.sp[s2];
+      if (s2 < chemgpu::kMaxSide) mt.y |= v << (8 * s2);
+      else mt.z |= v << (8 * (s2 - chemgpu::kMaxSide));
+    }
+    mt.w = d.eff_off | (d.eff_n << 20);
+    rmeta[j] = mt;
+  }
   // per-species lists of (reaction, net coefficient) in reaction order; for
   // each group width the list is split in chunks of that many reactions
   std::vector<int> ent, ent_start(S + 1, 0);
@@ -326,7 +349,10 @@ int upload(chem_mech* h) {
   const size_t sz_effk = align(sizeof(int) * effk.size());
   const size_t o_effv = o_effk + sz_effk;
   const size_t sz_effv = align(sizeof(double) * effv.size());
-  const size_t total = o_effv + sz_effv;
+  const size_t sz_rk = align(sizeof(double) * rlnA.size());
+  const size_t o_rlnA = o_effv + sz_effv, o_rb = o_rlnA + sz_rk, o_rEaR = o_rb + sz_rk, o_rmeta = o_rEaR + sz_rk;
+  const size_t sz_rmeta = align(sizeof(int4) * rmeta.size());
+  const size_t total = o_rmeta + sz_rmeta;
   std::vector<char> blob(total, 0);
   double* sp = reinterpret_cast<double*>(blob.data() + o_sp);
   for (int k = 0; k < S; ++k) {
@@ -348,6 +374,10 @@ int upload(chem_mech* h) {
   }
   std::memcpy(blob.data() + o_effk, effk.data(), sizeof(int) * effk.size());
   std::memcpy(blob.data() + o_effv, effv.data(), sizeof(double) * effv.size());
+  std::memcpy(blob.data() + o_rlnA, rlnA.data(), sizeof(double) * rlnA.size());
+  std::memcpy(blob.data() + o_rb, rb.data(), sizeof(double) * rb.size());
+  std::memcpy(blob.data() + o_rEaR, rEaR.data(), sizeof(double) * rEaR.size());
+  std::memcpy(blob.data() + o_rmeta, rmeta.data(), sizeof(int4) * rmeta.size());
 
   hipError_t e = hipGetDevice(&h->device);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -387,6 +417,10 @@ int upload(chem_mech* h) {
   dm.nasa_c = nasa ? reinterpret_cast<const double*>(base + o_nasa) : nullptr;
   dm.eff_k = reinterpret_cast<const int*>(base + o_effk);
   dm.eff_v = reinterpret_cast<const double*>(base + o_effv);
+  dm.rx_lnA = reinterpret_cast<const double*>(base + o_rlnA);
+  dm.rx_b = reinterpret_cast<const double*>(base + o_rb);
+  dm.rx_EaR = reinterpret_cast<const double*>(base + o_rEaR);
+  dm.rx_meta = reinterpret_cast<const int4*>(base + o_rmeta);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, h->device) == hipSuccess && prop.multiProcessorCount > 0)
     h->n_cu = prop.multiProcessorCount;

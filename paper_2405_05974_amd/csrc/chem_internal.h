@@ -55,7 +55,21 @@ struct DevMech {
   const double* nasa_c;    // [15][S]: T_mid, then c1..c7 for T <= T_mid, then c1..c7 above
   const int* eff_k;        // collision efficiencies other than 1: species index
   const double* eff_v;     //   and efficiency minus 1
+  // The fields every rate evaluation reads, one array per field (reaction j
+  // at j), so that the lanes of a wave, which hold consecutive reactions,
+  // read them with coalesced loads:
+  const double* rx_lnA;    // [R] ln A, temperature exponent, Ea/R
+  const double* rx_b;
+  const double* rx_EaR;
+  const int4* rx_meta;     // [R] x: type | rev << 2 | nr << 3 | np << 5 | (ntroe > 0) << 7
+                           //     y, z: species of slots 0..2 and 3..5, 8 bits each (255 = none)
+                           //     w: eff_off | eff_n << 20
 };
+
+__host__ __device__ inline int meta_slot(const int4& mt, const int s) {
+  const int v = ((s < kMaxSide ? mt.y : mt.z) >> (8 * (s % kMaxSide))) & 255;
+  return v == 255 ? -1 : v;
+}
 
 // One box of the batched entry point, in queue order.
 struct BoxDev {

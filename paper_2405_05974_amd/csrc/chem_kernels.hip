@@ -356,15 +356,18 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
 #pragma unroll
     for (int s = 0; s < kSlots; ++s) dq[s] = 0.0;
     if (j < m.R) {
-      const RxParams& x = m.rx[j];
-      const int type = x.type, nr = x.nr, np = x.np;
+      const int4 mt = m.rx_meta[j];
+      const int type = mt.x & 3, rev = (mt.x >> 2) & 1, nr = (mt.x >> 3) & 3, np = (mt.x >> 5) & 3;
+      const int eff_off = mt.w & 0xFFFFF, eff_n = mt.w >> 20;
+      const double xb = m.rx_b[j], xEaR = m.rx_EaR[j];
       // third-body concentration with this reaction's efficiencies
       double Mj = Mconc;
-      for (int i = 0; i < x.eff_n; ++i) Mj += m.eff_v[x.eff_off + i] * sh.C[base + m.eff_k[x.eff_off + i]];
-      const double kinf = exp(x.lnA + x.b * lnT - x.EaR * invT);
-      double dlnkf = (x.b + x.EaR * invT) * invT;
+      for (int i = 0; i < eff_n; ++i) Mj += m.eff_v[eff_off + i] * sh.C[base + m.eff_k[eff_off + i]];
+      const double kinf = exp(m.rx_lnA[j] + xb * lnT - xEaR * invT);
+      double dlnkf = (xb + xEaR * invT) * invT;
       double kf = kinf, dkfdM = 0.0;
-      if (type == 2) {
+      if (type == 2) {   // falloff: the rarer fields from the full record
+        const RxParams& x = m.rx[j];
         const double k0 = exp(x.lnA0 + x.b0 * lnT - x.EaR0 * invT);
         const double dlnk0 = (x.b0 + x.EaR0 * invT) * invT;
         const double Pr = k0 * Mj / kinf;
@@ -372,7 +375,7 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
         kf = kinf * Pr / (1.0 + Pr);
         dlnkf = dlnkf + dlnPr / (1.0 + Pr);
         dkfdM = k0 / ((1.0 + Pr) * (1.0 + Pr));
-        if (x.ntroe) {
+        if ((mt.x >> 7) & 1) {
           double F, dlnF, dlogF_dlp;
           troe_broadening<JAC>(x, T, Pr, dlnPr, F, dlnF, dlogF_dlp);
           if (JAC) {
@@ -384,7 +387,7 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
       }
       int sp[kSlots];
 #pragma unroll
-      for (int s = 0; s < kSlots; ++s) sp[s] = x.sp[s];
+      for (int s = 0; s < kSlots; ++s) sp[s] = meta_slot(mt, s);
       double cs[kSlots];
 #pragma unroll
       for (int s = 0; s < kSlots; ++s) cs[s] = (sp[s] >= 0) ? sh.C[base + sp[s]] : 1.0;
@@ -395,7 +398,7 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
         if (s < np) pr *= cs[kMaxSide + s];
       }
       double kr = 0.0, dkr = 0.0, dkrdM = 0.0;
-      if (x.rev) {
+      if (rev) {
         double sg = 0.0, shh = 0.0;
 #pragma unroll
         for (int s = 0; s < kMaxSide; ++s) {
@@ -463,16 +466,16 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
         if (JAC) {
           bT += nu * rq[1 * kWave + src];
           ak += nu * rq[2 * kWave + src];
-          const int* sp = m.rx[jj].sp;
+          const int4 mt = m.rx_meta[jj];
 #pragma unroll
           for (int s = 0; s < kSlots; ++s) {
-            const int c = sp[s];
+            const int c = meta_slot(mt, s);
             if (c >= 0)
               __hip_atomic_fetch_add(&Jg[r * sh.ldj + c], nu * rq[(3 + s) * kWave + src], __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_WAVEFRONT);
           }
           // efficiencies other than 1: d[M]_j/dC_c = 1 + (eps_jc - 1), the 1 being the rank-one part in ak
-          const int eo = m.rx[jj].eff_off, en = m.rx[jj].eff_n;
+          const int eo = mt.w & 0xFFFFF, en = mt.w >> 20;
           for (int i = 0; i < en; ++i)
             __hip_atomic_fetch_add(&Jg[r * sh.ldj + m.eff_k[eo + i]], nu * rq[2 * kWave + src] * m.eff_v[eo + i],
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
