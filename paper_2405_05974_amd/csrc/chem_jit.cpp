@@ -193,10 +193,10 @@ std::string lpc_source(const HostMech& m_in, bool reuse) {
   o << "template <bool JAC, bool WD = false>\n__device__ __forceinline__ void ch_eval(const double (&y)[CH_N], "
        "const double p, const int fixedT, double (&f)[CH_N], double (&J)[CH_N][CH_N], double* wdo = nullptr) {\n";
   // K reads the table through the constant address space, so loads stay scalar.  At the top
-  // and before each reaction the pointer passes through an empty asm statement: the compiler
-  // can no longer hoist every table load out of the step loop (about 130 doubles kept live in
-  // scalar registers and spilled), and loads each reaction's constants from the scalar cache
-  // where they are used.
+  // and before every fourth reaction the pointer passes through an empty asm statement: the
+  // compiler can no longer hoist every table load out of the step loop (about 130 doubles kept
+  // live in scalar registers and spilled), and loads each group's constants from the scalar
+  // cache where they are used.
   o << "  typedef const __attribute__((address_space(4))) double* ch_kptr;\n";
   o << "  ch_kptr __restrict__ K = (ch_kptr)ch_K;\n  asm volatile(\"\" : \"+s\"(K));\n";
   o << "  const double T = y[CH_S];\n  const double lnT = log(T);\n  const double invT = 1.0 / T;\n";
@@ -439,7 +439,11 @@ std::string lpc_source(const HostMech& m_in, bool reuse) {
     const HostReaction& x = m.rx[j];
     const std::vector<int> nu = nu_of(x);
     const int dnu = (int)x.prod.size() - (int)x.reac.size();
-    o << "  asm volatile(\"\" : \"+s\"(K));\n  {  // reaction " << j << "\n";
+    // the table pointer is made opaque every 4 reactions: their constants are
+    // loaded together, and not all at the top of the function (which would
+    // exhaust the scalar registers)
+    if (j % 4 == 0) o << "  asm volatile(\"\" : \"+s\"(K));\n";
+    o << "  {  // reaction " << j << "\n";
     emit_kf(x);
     // a direction removed by the linearisation has a zero concentration product
     o << "    const double pf = " << (x.drop_f ? std::string("0.0") : product(x.reac, -1)) << ";\n";
@@ -635,7 +639,11 @@ int lpc_module(const std::string& src, int device, void** integrate_fn, void** b
     return -1;
   }
   const std::string off = "--offload-arch=" + arch;
-  const char* opts[] = {off.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+  // Machine LICM off: with the whole integration in one loop nest it hoists
+  // constants and addresses out of the step loop, and with every register
+  // in use they are then spilled to scratch and reloaded at each use.
+  const char* opts[] = {off.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                        "-mllvm", "-disable-machine-licm"};
   const hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
   size_t log_size = 0;
   hiprtcGetProgramLogSize(prog, &log_size);
