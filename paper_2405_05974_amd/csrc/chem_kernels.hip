@@ -62,6 +62,10 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
 constexpr int kRor8 = 0x128, kRor4 = 0x124, kRor2 = 0x122, kRor1 = 0x121;
 
 // Sum over the group (all lanes receive the same bits).
@@ -561,20 +565,42 @@ __device__ __forceinline__ void factor_newton_matrix(const Shared& sh, const dou
     double cand = used ? -1.0 : fabs(a[k]);
     if (!(cand == cand)) cand = -1.0;
     const int idx = gpivot<NP>(cand);
-    double* prow = sh.prow + (k & 1) * kWave + base;
-    if (r == idx) {
-      used = true;
-      pos = k;
-      sh.perm[base + k] = r;
+    if constexpr (NP == kWave) {
+      // one cell per wave: the pivot lane is wave-uniform, and its row reaches
+      // every lane by readlane, straight into scalar registers; rows already
+      // used take the multiplier 0 and stay as they are (no branch, and no LDS
+      // round trip per column pair, which register pressure had serialised)
+      if (r == idx) {
+        used = true;
+        pos = k;
+        sh.perm[base + k] = r;
+      }
+      const double pk = readlane_d(a[k], idx);
+      const double l = used ? 0.0 : a[k] / pk;
+      if (!used) a[k] = l;
 #pragma unroll
-      for (int c = k; c < NP; ++c) prow[c] = a[c];
-    }
-    wave_sync();
-    if (!used) {
-      const double l = a[k] / prow[k];
-      a[k] = l;
+      for (int c = k + 1; c < NP; ++c) {
+        a[c] -= l * readlane_d(a[c], idx);
+        // keep the scheduler from hoisting a whole row of readlanes (each holds
+        // two scalar registers) ahead of their FMAs
+        if ((c & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+      double* prow = sh.prow + (k & 1) * kWave + base;
+      if (r == idx) {
+        used = true;
+        pos = k;
+        sh.perm[base + k] = r;
 #pragma unroll
-      for (int c = k + 1; c < NP; ++c) a[c] -= l * prow[c];
+        for (int c = k; c < NP; ++c) prow[c] = a[c];
+      }
+      wave_sync();
+      if (!used) {
+        const double l = a[k] / prow[k];
+        a[k] = l;
+#pragma unroll
+        for (int c = k + 1; c < NP; ++c) a[c] -= l * prow[c];
+      }
     }
   }
   // store the rows in pivot order (every lane pivots exactly once).  The
@@ -688,20 +714,36 @@ __device__ __forceinline__ void factor_newton_matrix_f32(const Shared& sh, const
     double cand = used ? -1.0 : (double)fabsf(a[k]);
     if (!(cand == cand)) cand = -1.0;
     const int idx = gpivot<NP>(cand);
-    float* prow = sh.prow32 + (k & 1) * kWave + base;
-    if (r == idx) {
-      used = true;
-      pos = k;
-      sh.perm[base + k] = r;
+    if constexpr (NP == kWave) {   // pivot row by readlane, as in the FP64 factorisation
+      if (r == idx) {
+        used = true;
+        pos = k;
+        sh.perm[base + k] = r;
+      }
+      const float pk = readlane_f(a[k], idx);
+      const float l = used ? 0.0f : a[k] / pk;
+      if (!used) a[k] = l;
 #pragma unroll
-      for (int c = k; c < NP; ++c) prow[c] = a[c];
-    }
-    wave_sync();
-    if (!used) {
-      const float l = a[k] / prow[k];
-      a[k] = l;
+      for (int c = k + 1; c < NP; ++c) {
+        a[c] -= l * readlane_f(a[c], idx);
+        if ((c & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+      float* prow = sh.prow32 + (k & 1) * kWave + base;
+      if (r == idx) {
+        used = true;
+        pos = k;
+        sh.perm[base + k] = r;
 #pragma unroll
-      for (int c = k + 1; c < NP; ++c) a[c] -= l * prow[c];
+        for (int c = k; c < NP; ++c) prow[c] = a[c];
+      }
+      wave_sync();
+      if (!used) {
+        const float l = a[k] / prow[k];
+        a[k] = l;
+#pragma unroll
+        for (int c = k + 1; c < NP; ++c) a[c] -= l * prow[c];
+      }
     }
   }
   if (pos >= 0 && pos < sh.rows) {
