@@ -322,6 +322,13 @@ int upload(chem_mech* h) {
       }
   }
   if (ent.empty()) ent.push_back(0);
+  // each entry with its reaction's species slots and efficiency list, so that
+  // the Jacobian scatter reads one 16-byte record per entry
+  std::vector<int4> ent4(ent.size());
+  for (size_t e = 0; e < ent.size(); ++e) {
+    const int4 mt = R > 0 ? rmeta[(size_t)(ent[e] >> 3)] : int4{0, 0xFFFFFF, 0xFFFFFF, 0};
+    ent4[e] = int4{ent[e], mt.y, mt.z, mt.w};
+  }
   std::vector<int> off;
   size_t off_at[3];
   for (int wi = 0; wi < 3; ++wi) {
@@ -352,7 +359,9 @@ int upload(chem_mech* h) {
   const size_t sz_rk = align(sizeof(double) * rlnA.size());
   const size_t o_rlnA = o_effv + sz_effv, o_rb = o_rlnA + sz_rk, o_rEaR = o_rb + sz_rk, o_rmeta = o_rEaR + sz_rk;
   const size_t sz_rmeta = align(sizeof(int4) * rmeta.size());
-  const size_t total = o_rmeta + sz_rmeta;
+  const size_t o_ent4 = o_rmeta + sz_rmeta;
+  const size_t sz_ent4 = align(sizeof(int4) * ent4.size());
+  const size_t total = o_ent4 + sz_ent4;
   std::vector<char> blob(total, 0);
   double* sp = reinterpret_cast<double*>(blob.data() + o_sp);
   for (int k = 0; k < S; ++k) {
@@ -378,6 +387,7 @@ int upload(chem_mech* h) {
   std::memcpy(blob.data() + o_rb, rb.data(), sizeof(double) * rb.size());
   std::memcpy(blob.data() + o_rEaR, rEaR.data(), sizeof(double) * rEaR.size());
   std::memcpy(blob.data() + o_rmeta, rmeta.data(), sizeof(int4) * rmeta.size());
+  std::memcpy(blob.data() + o_ent4, ent4.data(), sizeof(int4) * ent4.size());
 
   hipError_t e = hipGetDevice(&h->device);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -407,6 +417,7 @@ int upload(chem_mech* h) {
   dm.csr_off = h->csr_off_np[np == 16 ? 0 : (np == 32 ? 1 : 2)];
   dm.nch = h->nch_np[np == 16 ? 0 : (np == 32 ? 1 : 2)];
   dm.csr_ent = reinterpret_cast<const int*>(base + o_ent);
+  dm.csr_ent4 = reinterpret_cast<const int4*>(base + o_ent4);
   if (!m.qss.empty()) {
     // the state holds the transported species; QSS mechanisms run only in the
     // generated kernels, which carry the closure themselves

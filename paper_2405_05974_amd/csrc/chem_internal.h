@@ -51,6 +51,7 @@ struct DevMech {
   const RxParams* rx;      // [R]
   const int* csr_off;      // [S * (nch + 1)] start of species k's entries in chunk c
   const int* csr_ent;      // entries (j << 3) | (nu_kj + 4), sorted by j per species
+  const int4* csr_ent4;    // the same entries with their reaction's metadata: (entry, rx_meta[j].y, .z, .w)
   int nasa;                // 1: every species' thermo from nasa_c (NASA 7-coefficient polynomials)
   const double* nasa_c;    // [15][S]: T_mid, then c1..c7 for T <= T_mid, then c1..c7 above
   const int* eff_k;        // collision efficiencies other than 1: species index

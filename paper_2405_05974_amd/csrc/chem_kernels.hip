@@ -461,8 +461,13 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
     if (isSp) {
       const int* off = m.csr_off + r * (m.nch + 1) + ch;
       const int e0 = off[0], e1 = off[1];
+      // one 16-byte record per entry (entry word and its reaction's metadata),
+      // the next one requested while this one is processed
+      int4 nxt = e0 < e1 ? m.csr_ent4[e0] : int4{0, 0, 0, 0};
       for (int e = e0; e < e1; ++e) {
-        const int ent = m.csr_ent[e];
+        const int4 mt = nxt;
+        if (e + 1 < e1) nxt = m.csr_ent4[e + 1];
+        const int ent = mt.x;
         const int jj = ent >> 3;
         const double nu = (double)((ent & 7) - 4);
         const int src = base + (jj - ch * NP);
@@ -470,7 +475,6 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
         if (JAC) {
           bT += nu * rq[1 * kWave + src];
           ak += nu * rq[2 * kWave + src];
-          const int4 mt = m.rx_meta[jj];
 #pragma unroll
           for (int s = 0; s < kSlots; ++s) {
             const int c = meta_slot(mt, s);
