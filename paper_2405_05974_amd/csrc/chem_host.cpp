@@ -291,6 +291,27 @@ int upload(chem_mech* h) {
     mt.w = d.eff_off | (d.eff_n << 20);
     rmeta[j] = mt;
   }
+  // net stoichiometry of each reaction (species order), for the Jacobian scatter
+  std::vector<int2> rnet(std::max(R, 1), int2{0x3FFFFFFF, 0x3FFFFFFF});
+  for (int j = 0; j < R; ++j) {
+    int2 nt{0, 0};
+    int cnt = 0;
+    for (int k = 0; k < S; ++k) {
+      int nu = 0;
+      for (int sp2 : m.rx[j].prod) nu += (sp2 == k);
+      for (int sp2 : m.rx[j].reac) nu -= (sp2 == k);
+      if (nu == 0) continue;
+      const int v = (k << 3) | (nu + 4);
+      if (cnt < 3) nt.x |= v << (10 * cnt);
+      else nt.y |= v << (10 * (cnt - 3));
+      ++cnt;
+    }
+    for (int c2 = cnt; c2 < 6; ++c2) {
+      if (c2 < 3) nt.x |= 1023 << (10 * c2);
+      else nt.y |= 1023 << (10 * (c2 - 3));
+    }
+    rnet[j] = nt;
+  }
   // per-species lists of (reaction, net coefficient) in reaction order; for
   // each group width the list is split in chunks of that many reactions
   std::vector<int> ent, ent_start(S + 1, 0);
@@ -322,13 +343,6 @@ int upload(chem_mech* h) {
       }
   }
   if (ent.empty()) ent.push_back(0);
-  // each entry with its reaction's species slots and efficiency list, so that
-  // the Jacobian scatter reads one 16-byte record per entry
-  std::vector<int4> ent4(ent.size());
-  for (size_t e = 0; e < ent.size(); ++e) {
-    const int4 mt = R > 0 ? rmeta[(size_t)(ent[e] >> 3)] : int4{0, 0xFFFFFF, 0xFFFFFF, 0};
-    ent4[e] = int4{ent[e], mt.y, mt.z, mt.w};
-  }
   std::vector<int> off;
   size_t off_at[3];
   for (int wi = 0; wi < 3; ++wi) {
@@ -359,9 +373,9 @@ int upload(chem_mech* h) {
   const size_t sz_rk = align(sizeof(double) * rlnA.size());
   const size_t o_rlnA = o_effv + sz_effv, o_rb = o_rlnA + sz_rk, o_rEaR = o_rb + sz_rk, o_rmeta = o_rEaR + sz_rk;
   const size_t sz_rmeta = align(sizeof(int4) * rmeta.size());
-  const size_t o_ent4 = o_rmeta + sz_rmeta;
-  const size_t sz_ent4 = align(sizeof(int4) * ent4.size());
-  const size_t total = o_ent4 + sz_ent4;
+  const size_t o_rnet = o_rmeta + sz_rmeta;
+  const size_t sz_rnet = align(sizeof(int2) * rnet.size());
+  const size_t total = o_rnet + sz_rnet;
   std::vector<char> blob(total, 0);
   double* sp = reinterpret_cast<double*>(blob.data() + o_sp);
   for (int k = 0; k < S; ++k) {
@@ -387,7 +401,7 @@ int upload(chem_mech* h) {
   std::memcpy(blob.data() + o_rb, rb.data(), sizeof(double) * rb.size());
   std::memcpy(blob.data() + o_rEaR, rEaR.data(), sizeof(double) * rEaR.size());
   std::memcpy(blob.data() + o_rmeta, rmeta.data(), sizeof(int4) * rmeta.size());
-  std::memcpy(blob.data() + o_ent4, ent4.data(), sizeof(int4) * ent4.size());
+  std::memcpy(blob.data() + o_rnet, rnet.data(), sizeof(int2) * rnet.size());
 
   hipError_t e = hipGetDevice(&h->device);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -417,7 +431,6 @@ int upload(chem_mech* h) {
   dm.csr_off = h->csr_off_np[np == 16 ? 0 : (np == 32 ? 1 : 2)];
   dm.nch = h->nch_np[np == 16 ? 0 : (np == 32 ? 1 : 2)];
   dm.csr_ent = reinterpret_cast<const int*>(base + o_ent);
-  dm.csr_ent4 = reinterpret_cast<const int4*>(base + o_ent4);
   if (!m.qss.empty()) {
     // the state holds the transported species; QSS mechanisms run only in the
     // generated kernels, which carry the closure themselves
@@ -432,6 +445,7 @@ int upload(chem_mech* h) {
   dm.rx_b = reinterpret_cast<const double*>(base + o_rb);
   dm.rx_EaR = reinterpret_cast<const double*>(base + o_rEaR);
   dm.rx_meta = reinterpret_cast<const int4*>(base + o_rmeta);
+  dm.rx_net = reinterpret_cast<const int2*>(base + o_rnet);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, h->device) == hipSuccess && prop.multiProcessorCount > 0)
     h->n_cu = prop.multiProcessorCount;

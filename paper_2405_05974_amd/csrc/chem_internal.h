@@ -51,7 +51,6 @@ struct DevMech {
   const RxParams* rx;      // [R]
   const int* csr_off;      // [S * (nch + 1)] start of species k's entries in chunk c
   const int* csr_ent;      // entries (j << 3) | (nu_kj + 4), sorted by j per species
-  const int4* csr_ent4;    // the same entries with their reaction's metadata: (entry, rx_meta[j].y, .z, .w)
   int nasa;                // 1: every species' thermo from nasa_c (NASA 7-coefficient polynomials)
   const double* nasa_c;    // [15][S]: T_mid, then c1..c7 for T <= T_mid, then c1..c7 above
   const int* eff_k;        // collision efficiencies other than 1: species index
@@ -65,7 +64,15 @@ struct DevMech {
   const int4* rx_meta;     // [R] x: type | rev << 2 | nr << 3 | np << 5 | (ntroe > 0) << 7
                            //     y, z: species of slots 0..2 and 3..5, 8 bits each (255 = none)
                            //     w: eff_off | eff_n << 20
+  const int2* rx_net;      // [R] the species with a nonzero net coefficient, up to 6, 10 bits each
+                           //     (species << 3 | nu + 4; 1023 = none), three in x and three in y
 };
+
+__host__ __device__ inline void net_slot(const int2& nt, const int p, int& k, int& nu) {
+  const int v = ((p < 3 ? nt.x : nt.y) >> (10 * (p % 3))) & 1023;
+  k = v == 1023 ? -1 : (v >> 3);
+  nu = (v & 7) - 4;
+}
 
 __host__ __device__ inline int meta_slot(const int4& mt, const int s) {
   const int v = ((s < kMaxSide ? mt.y : mt.z) >> (8 * (s % kMaxSide))) & 255;

@@ -6,7 +6,8 @@
 // lanes (reaction j on lane j mod NP, in chunks of NP); species
 // concentrations and Gibbs energies are exchanged through LDS, production
 // rates are gathered per species lane in reaction order, and the sparse part
-// of the Jacobian is scattered into per-cell LDS rows with f64 LDS atomics.
+// of the Jacobian is scattered by the reaction lanes into per-cell LDS rows
+// with f64 LDS atomics.
 // The Newton matrix lives in those LDS rows between phases and is factored in
 // registers (one row per lane) with partial pivoting; the factors are stored
 // back in pivot order so that the triangular solves broadcast from fixed
@@ -206,7 +207,7 @@ struct Shared {
   double* W;      // [64] molecular weights (written once per kernel)
   double* iW;     // [64] 1/W_c for species columns, 0 for the T and padding columns
   double* isT;    // [64] 1 for the temperature column, else 0
-  double* rq;     // [9][64]: Q, dQ/dT, q0, dQ/dC slots 0..5
+  double* rq;     // [3][64]: Q, dQ/dT, q0 of each lane's reaction
   double* prow;   // [2][64] pivot row, double-buffered
   int* perm;      // [64] lane whose row holds pivot k
   float* F;       // [groups][rows][ldj] FP32 LU factors (mixed-precision option only)
@@ -226,7 +227,7 @@ __device__ __forceinline__ Shared carve(double* smem, int NP, int N, bool f32 = 
   s.iW = s.W + kWave;
   s.isT = s.iW + kWave;
   s.rq = s.isT + kWave;
-  s.prow = s.rq + 9 * kWave;
+  s.prow = s.rq + 3 * kWave;
   s.perm = reinterpret_cast<int*>(s.prow + 2 * kWave);
   s.J = s.prow + 2 * kWave + kWave / 2;   // perm takes 64 ints = 32 doubles
   const size_t jd = (size_t)(kWave / NP) * N * (NP + 1);
@@ -240,7 +241,7 @@ __device__ __forceinline__ Shared carve(double* smem, int NP, int N, bool f32 = 
 size_t integrate_lds_bytes(int np_width, int N, bool f32) {
   const int groups = kWave / np_width;
   const size_t jd = (size_t)groups * N * (np_width + 1);
-  const size_t doubles = 6 * kWave + 9 * kWave + 2 * kWave + kWave / 2 + jd;
+  const size_t doubles = 6 * kWave + 3 * kWave + 2 * kWave + kWave / 2 + jd;
   return doubles * sizeof(double) + (f32 ? (jd + 2 * kWave) * sizeof(float) : 0);
 }
 
@@ -294,7 +295,8 @@ __device__ __forceinline__ void troe_broadening(const RxParams& x, const double 
 //   Eq. 3: wdot_k = sum_j nu_kj Q_j
 //   dY_k/dt = W_k wdot_k / rho,  dT/dt = -sum H_k wdot_k / sum C_k Cp_k
 // The Jacobian (Eq. 7 in the state (Y, T)) is assembled from the sparse
-// concentration-space part A = dwdot/dC (slot products, scattered in LDS), the
+// concentration-space part A = dwdot/dC (slot products, scattered in LDS by
+// each reaction lane into its participants' rows), the
 // rank-1 part of [M] (its unit part; efficiencies other than 1 are scattered
 // as sparse corrections), the closed-form T derivatives, and
 // the chain rule through C_k(Y, T) and rho(Y, T).
@@ -454,20 +456,40 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
     if (JAC) {
       rq[1 * kWave + lane] = dQdT;
       rq[2 * kWave + lane] = q0;
+      // concentration-space Jacobian, reaction by reaction: the row of every
+      // species k with a nonzero net coefficient nu_kj gets nu_kj dQ/dC_c for
+      // each slot species c, added into the group's LDS rows; with
+      // efficiencies other than 1 also nu_kj q0 (eps_jc - 1) in column c (the
+      // 1 is the rank-one part of [M])
+      if (j < m.R) {
+        const int4 mt = m.rx_meta[j];
+        const int2 nt = m.rx_net[j];
+        const int eo = mt.w & 0xFFFFF, en = mt.w >> 20;
 #pragma unroll
-      for (int s = 0; s < kSlots; ++s) rq[(3 + s) * kWave + lane] = dq[s];
+        for (int p = 0; p < kSlots; ++p) {
+          int kp, nup;
+          net_slot(nt, p, kp, nup);
+          if (kp < 0) continue;
+          const double nu = (double)nup;
+#pragma unroll
+          for (int s = 0; s < kSlots; ++s) {
+            const int c = meta_slot(mt, s);
+            if (c >= 0)
+              __hip_atomic_fetch_add(&Jg[kp * sh.ldj + c], nu * dq[s], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WAVEFRONT);
+          }
+          for (int i = 0; i < en; ++i)
+            __hip_atomic_fetch_add(&Jg[kp * sh.ldj + m.eff_k[eo + i]], nu * q0 * m.eff_v[eo + i],
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        }
+      }
     }
     wave_sync();
     if (isSp) {
       const int* off = m.csr_off + r * (m.nch + 1) + ch;
       const int e0 = off[0], e1 = off[1];
-      // one 16-byte record per entry (entry word and its reaction's metadata),
-      // the next one requested while this one is processed
-      int4 nxt = e0 < e1 ? m.csr_ent4[e0] : int4{0, 0, 0, 0};
       for (int e = e0; e < e1; ++e) {
-        const int4 mt = nxt;
-        if (e + 1 < e1) nxt = m.csr_ent4[e + 1];
-        const int ent = mt.x;
+        const int ent = m.csr_ent[e];
         const int jj = ent >> 3;
         const double nu = (double)((ent & 7) - 4);
         const int src = base + (jj - ch * NP);
@@ -475,18 +497,6 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
         if (JAC) {
           bT += nu * rq[1 * kWave + src];
           ak += nu * rq[2 * kWave + src];
-#pragma unroll
-          for (int s = 0; s < kSlots; ++s) {
-            const int c = meta_slot(mt, s);
-            if (c >= 0)
-              __hip_atomic_fetch_add(&Jg[r * sh.ldj + c], nu * rq[(3 + s) * kWave + src], __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_WAVEFRONT);
-          }
-          // efficiencies other than 1: d[M]_j/dC_c = 1 + (eps_jc - 1), the 1 being the rank-one part in ak
-          const int eo = mt.w & 0xFFFFF, en = mt.w >> 20;
-          for (int i = 0; i < en; ++i)
-            __hip_atomic_fetch_add(&Jg[r * sh.ldj + m.eff_k[eo + i]], nu * rq[2 * kWave + src] * m.eff_v[eo + i],
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         }
       }
     }
