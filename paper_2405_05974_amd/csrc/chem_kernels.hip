@@ -593,12 +593,7 @@ __device__ __forceinline__ void factor_newton_matrix(const Shared& sh, const dou
       const double l = used ? 0.0 : a[k] / pk;
       if (!used) a[k] = l;
 #pragma unroll
-      for (int c = k + 1; c < NP; ++c) {
-        a[c] -= l * readlane_d(a[c], idx);
-        // keep the scheduler from hoisting a whole row of readlanes (each holds
-        // two scalar registers) ahead of their FMAs
-        if ((c & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-      }
+      for (int c = k + 1; c < NP; ++c) a[c] -= l * readlane_d(a[c], idx);
     } else {
       double* prow = sh.prow + (k & 1) * kWave + base;
       if (r == idx) {
@@ -738,10 +733,7 @@ __device__ __forceinline__ void factor_newton_matrix_f32(const Shared& sh, const
       const float l = used ? 0.0f : a[k] / pk;
       if (!used) a[k] = l;
 #pragma unroll
-      for (int c = k + 1; c < NP; ++c) {
-        a[c] -= l * readlane_f(a[c], idx);
-        if ((c & 7) == 7) __builtin_amdgcn_sched_barrier(0);
-      }
+      for (int c = k + 1; c < NP; ++c) a[c] -= l * readlane_f(a[c], idx);
     } else {
       float* prow = sh.prow32 + (k & 1) * kWave + base;
       if (r == idx) {
