@@ -160,9 +160,6 @@ hipError_t launch_serve(const DevMech& m, const IntParams& prm, const ServeQueue
 int serve_waves_per_cu(const DevMech& m, bool f32);
 // Zero `count` unsigned words of device memory with a kernel (no memset node).
 hipError_t launch_zero_u32(unsigned* p, int count, hipStream_t stream);
-// Copy `count` 32-bit words with a kernel (device or host-mapped memory on
-// either side); ordinary stores, so a later kernel on the device sees them.
-hipError_t launch_copy_words(uint32_t* dst, const uint32_t* src, int64_t count, hipStream_t stream);
 
 // Lane-per-cell kernels, generated per mechanism and compiled with hipRTC
 // (chem_jit.cpp).  Largest state size N = S + 1 they serve.

@@ -16,7 +16,6 @@
 // same expression on the same operands, so group decisions never split.
 #include "chem_internal.h"
 
-#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -1306,10 +1305,6 @@ __global__ void zero_u32_kernel(unsigned* __restrict__ p, const int count) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0u;
 }
 
-__global__ void copy_words_kernel(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src, const int64_t count) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) dst[i] = src[i];
-}
 
 // Queue counters for boxes_kernel: head = 0, remaining[i] = tiles of box i.
 __global__ void boxes_init_kernel(const BoxDev* __restrict__ boxes, const BoxJob* __restrict__ job,
@@ -1489,13 +1484,6 @@ hipError_t launch_zero_u32(unsigned* p, int count, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(zero_u32_kernel, dim3((count + 255) / 256 < 64 ? (count + 255) / 256 : 64), dim3(256), 0, stream,
                      p, count);
-  return hipGetLastError();
-}
-
-hipError_t launch_copy_words(uint32_t* dst, const uint32_t* src, int64_t count, hipStream_t stream) {
-  if (count <= 0) return hipSuccess;
-  const int64_t blocks = std::min<int64_t>((count + 1023) / 1024, 4096);
-  hipLaunchKernelGGL(copy_words_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, dst, src, count);
   return hipGetLastError();
 }
 
