@@ -206,7 +206,7 @@ struct Shared {
   double* W;      // [64] molecular weights (written once per kernel)
   double* iW;     // [64] 1/W_c for species columns, 0 for the T and padding columns
   double* isT;    // [64] 1 for the temperature column, else 0
-  double* rq;     // [3][64]: Q, dQ/dT, q0 of each lane's reaction
+  double* rq;     // [3][64]: per species, sums of nu Q, nu dQ/dT and nu q0 over the reactions
   double* prow;   // [2][64] pivot row, double-buffered
   int* perm;      // [64] lane whose row holds pivot k
   float* F;       // [groups][rows][ldj] FP32 LU factors (mixed-precision option only)
@@ -344,6 +344,10 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
   sh.C[lane] = C;
   sh.G[lane] = Gd;
   sh.H[lane] = H;
+  // per-species sums of nu Q, nu dQ/dT and nu q0, added by the reaction lanes
+  sh.rq[0 * kWave + lane] = 0.0;
+  sh.rq[1 * kWave + lane] = 0.0;
+  sh.rq[2 * kWave + lane] = 0.0;
   if (JAC && r < sh.rows) {
 #pragma unroll
     for (int c = 0; c < NP; ++c) Jg[r * sh.ldj + c] = 0.0;
@@ -451,25 +455,28 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
         }
       }
     }
-    rq[0 * kWave + lane] = Q;
-    if (JAC) {
-      rq[1 * kWave + lane] = dQdT;
-      rq[2 * kWave + lane] = q0;
-      // concentration-space Jacobian, reaction by reaction: the row of every
-      // species k with a nonzero net coefficient nu_kj gets nu_kj dQ/dC_c for
-      // each slot species c, added into the group's LDS rows; with
-      // efficiencies other than 1 also nu_kj q0 (eps_jc - 1) in column c (the
-      // 1 is the rank-one part of [M])
-      if (j < m.R) {
-        const int4 mt = m.rx_meta[j];
-        const int2 nt = m.rx_net[j];
-        const int eo = mt.w & 0xFFFFF, en = mt.w >> 20;
+    // production rates and, for JAC, the concentration-space Jacobian,
+    // reaction by reaction: every species k with a nonzero net coefficient
+    // nu_kj gets nu_kj Q_j (and nu_kj dQ_j/dT, nu_kj q0_j) in its sums and
+    // nu_kj dQ_j/dC_c for each slot species c in its LDS row; with
+    // efficiencies other than 1 also nu_kj q0 (eps_jc - 1) in column c (the 1
+    // is the rank-one part of [M])
+    if (j < m.R) {
+      const int4 mt = m.rx_meta[j];
+      const int2 nt = m.rx_net[j];
+      const int eo = mt.w & 0xFFFFF, en = mt.w >> 20;
 #pragma unroll
-        for (int p = 0; p < kSlots; ++p) {
-          int kp, nup;
-          net_slot(nt, p, kp, nup);
-          if (kp < 0) continue;
-          const double nu = (double)nup;
+      for (int p = 0; p < kSlots; ++p) {
+        int kp, nup;
+        net_slot(nt, p, kp, nup);
+        if (kp < 0) continue;
+        const double nu = (double)nup;
+        __hip_atomic_fetch_add(&rq[0 * kWave + base + kp], nu * Q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (JAC) {
+          __hip_atomic_fetch_add(&rq[1 * kWave + base + kp], nu * dQdT, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WAVEFRONT);
+          __hip_atomic_fetch_add(&rq[2 * kWave + base + kp], nu * q0, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WAVEFRONT);
 #pragma unroll
           for (int s = 0; s < kSlots; ++s) {
             const int c = meta_slot(mt, s);
@@ -483,23 +490,14 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
         }
       }
     }
-    wave_sync();
-    if (isSp) {
-      const int* off = m.csr_off + r * (m.nch + 1) + ch;
-      const int e0 = off[0], e1 = off[1];
-      for (int e = e0; e < e1; ++e) {
-        const int ent = m.csr_ent[e];
-        const int jj = ent >> 3;
-        const double nu = (double)((ent & 7) - 4);
-        const int src = base + (jj - ch * NP);
-        wd += nu * rq[src];
-        if (JAC) {
-          bT += nu * rq[1 * kWave + src];
-          ak += nu * rq[2 * kWave + src];
-        }
-      }
+  }
+  wave_sync();
+  if (isSp) {
+    wd = rq[0 * kWave + lane];
+    if (JAC) {
+      bT = rq[1 * kWave + lane];
+      ak = rq[2 * kWave + lane];
     }
-    wave_sync();
   }
 
   // ODE right-hand side
