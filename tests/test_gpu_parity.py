@@ -370,11 +370,17 @@ def test_integration_at_pressure(chem, torch_dev, p, kernel):
 # implementations' finite-difference Jacobians differ at that level.  Newton
 # then stops at different iterates within its tolerance and later step
 # decisions can differ: the results agree to the integration accuracy, not to
-# rounding.  On these inputs the oracle's own finite-difference runs are within
-# 1.3e-7 (T) and 2.3e-8 (Y) of the tight-tolerance truth; the bar below allows
-# the GPU the same distance from the oracle and from the truth.
+# rounding.  The oracle itself shows the size of that scatter: with only the
+# order of the reactions changed (so only the summation order of the
+# production rates), its finite-difference results on this config-1 sample
+# move by up to 8.6e-7 in T/T and 1.5e-8 in Y, and land up to 7.3e-7 (T) from
+# the tight-tolerance truth (tests/test_oracle.py::
+# test_difference_quotient_scatter_under_summation_order pins a bounded
+# version of this).  The bar allows the GPU the same distance from the truth,
+# E = 1e-7 in Y and 1e-6 in T/T, and so 2E from the oracle (two results
+# within E of the truth are within 2E of each other).
 TOL_FD_Y = 1e-7
-TOL_FD_T = 3e-7
+TOL_FD_T = 1e-6
 
 
 @pytest.mark.parametrize("mode", [1, 2], ids=["fd", "fd_T"])
@@ -393,11 +399,11 @@ def test_difference_quotient_jacobian_parity(chem, torch_dev, mode):
     To, Yo, so = oracle_integrate(text, w.T[idx], w.Y[:, idx], w.p, w.dt, w.rtol, w.atol, jac_mode=mode)
     Tt, Yt, _ = oracle.Mech(text).integrate(w.T[idx], w.Y[:, idx], w.p, w.dt, 1e-12, 1e-20)
     assert st["rc"] == 0 and (rec[0] == 0).all()
-    for what, (Ta, Ya, Tb, Yb) in (("vs oracle", (Tg, Yg, To, Yo)), ("vs truth", (Tg, Yg, Tt, Yt))):
+    for what, (Ta, Ya, Tb, Yb), k in (("vs oracle", (Tg, Yg, To, Yo), 2), ("vs truth", (Tg, Yg, Tt, Yt), 1)):
         dY = np.abs(Ya - Yb).max()
         dT = (np.abs(Ta - Tb) / Tb).max()
         say(f"jacobian mode {mode} config1 {what}: max|dY|={dY:.3e} max|dT|/T={dT:.3e}")
-        assert dY <= TOL_FD_Y and dT <= TOL_FD_T, what
+        assert dY <= k * TOL_FD_Y and dT <= k * TOL_FD_T, what
     say(f"jacobian mode {mode}: steps gpu {rec[1].sum()} oracle {so['steps'].sum()}, "
         f"identical per cell {(rec[1] == so['steps']).mean():.3f}")
     assert abs(rec[1].sum() / so["steps"].sum() - 1) <= 0.05
@@ -414,7 +420,7 @@ def test_difference_quotient_jacobian_parity(chem, torch_dev, mode):
     dY = np.abs(Yg - Yo).max()
     dT = (np.abs(Tg - To) / To).max()
     say(f"jacobian mode {mode} config4 box: max|dY|={dY:.3e} max|dT|/T={dT:.3e}")
-    assert dY <= TOL_FD_Y and dT <= TOL_FD_T
+    assert dY <= 2 * TOL_FD_Y and dT <= 2 * TOL_FD_T
 
 
 # Kept Newton matrices (CHEM_OPT_JAC_REUSE) make Newton converge linearly, so

@@ -344,6 +344,47 @@ def test_integration_with_difference_quotient_jacobian(g10, g10_run, mode):
     assert (extra == per_jac * sf["n_jac"]).all()
 
 
+def test_difference_quotient_scatter_under_summation_order():
+    """The finite-difference Jacobian modes reproduce only to the integration
+    accuracy: with nothing changed but the order of the reactions (so the
+    summation order of the production rates, a rounding-level change), the
+    oracle's own results on a config-1 sample move by far more than rounding,
+    yet stay within the integration-accuracy bar of the GPU tests (1e-7 in Y,
+    1e-6 in T/T from the truth, twice that between two runs).  The default
+    analytic-Jacobian integrator, for contrast, moves only slightly."""
+    import copy
+    w = synth.config_workload(1)
+    idx = np.arange(0, w.n_cells, 16)
+    T0, Y0 = w.T[idx], w.Y[:, idx]
+    om = oracle.Mech(w.mech.to_text())
+    Tt, Yt, _ = om.integrate(T0, Y0, w.p, w.dt, 1e-12, 1e-20)
+    rng = np.random.default_rng(7)
+    perms = [rng.permutation(w.mech.n_reactions) for _ in range(4)]
+    mechs_p = []
+    for perm in perms:
+        m2 = copy.deepcopy(w.mech)
+        m2.reactions = [m2.reactions[i] for i in perm]
+        mechs_p.append(oracle.Mech(m2.to_text()))
+    spread = {}
+    for mode in (0, 1, 2):
+        To, Yo, _ = om.integrate(T0, Y0, w.p, w.dt, w.rtol, w.atol, jac_mode=mode)
+        dT = dY = dTt = dYt = 0.0
+        for o2 in mechs_p:
+            Tq, Yq, sq = o2.integrate(T0, Y0, w.p, w.dt, w.rtol, w.atol, jac_mode=mode)
+            assert (sq["status"] == 0).all()
+            dT = max(dT, (np.abs(Tq - To) / To).max())
+            dY = max(dY, np.abs(Yq - Yo).max())
+            dTt = max(dTt, (np.abs(Tq - Tt) / Tt).max())
+            dYt = max(dYt, np.abs(Yq - Yt).max())
+        spread[mode] = dT
+        assert dY <= 2e-7 and dT <= 2e-6, (mode, dY, dT)
+        assert dYt <= 1e-7 and dTt <= 1e-6, (mode, dYt, dTt)
+    # far more than rounding in the difference-quotient modes, while the
+    # analytic-Jacobian default stays inside its own 1e-8 parity bar
+    assert spread[1] > 5e-8 and spread[2] > 5e-8, spread
+    assert spread[0] <= 1e-8, spread
+
+
 # ----------------------------------------------------------- linear algebra
 
 def test_lu_matches_numpy():
