@@ -560,19 +560,22 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
 // LDS.  On return the LDS rows hold the factors in pivot order (row k = L row
 // k below the diagonal, U row k on and above it), perm[k] names the lane whose
 // original row became row k, and rdiag = 1/u_rr for lane r's position.
-template <int NP>
+// NC (a multiple of 8, N <= NC <= NP) is the number of columns carried: the
+// rows and columns NC..NP-1 hold only identity rows of padding lanes, and the
+// elimination steps k >= N change no stored row, so stopping at NC is exact.
+template <int NP, int NC = NP>
 __device__ __forceinline__ void factor_newton_matrix(const Shared& sh, const double cfac, double& rdiag) {
   const int lane = opaque_lane();
   const int r = lane % NP;
   const int base = lane - r;
   double* Jg = sh.J + (size_t)(lane / NP) * sh.rows * sh.ldj;
-  double a[NP];
+  double a[NC];
 #pragma unroll
-  for (int c = 0; c < NP; ++c) a[c] = ((c == r) ? 1.0 : 0.0) - (r < sh.rows ? cfac * Jg[r * sh.ldj + c] : 0.0);
+  for (int c = 0; c < NC; ++c) a[c] = ((c == r) ? 1.0 : 0.0) - (r < sh.rows ? cfac * Jg[r * sh.ldj + c] : 0.0);
   bool used = false;
   int pos = -1;
 #pragma unroll
-  for (int k = 0; k < NP; ++k) {
+  for (int k = 0; k < NC; ++k) {
     double cand = used ? -1.0 : fabs(a[k]);
     if (!(cand == cand)) cand = -1.0;
     const int idx = gpivot<NP>(cand);
@@ -590,7 +593,7 @@ __device__ __forceinline__ void factor_newton_matrix(const Shared& sh, const dou
       const double l = used ? 0.0 : a[k] / pk;
       if (!used) a[k] = l;
 #pragma unroll
-      for (int c = k + 1; c < NP; ++c) a[c] -= l * readlane_d(a[c], idx);
+      for (int c = k + 1; c < NC; ++c) a[c] -= l * readlane_d(a[c], idx);
     } else {
       double* prow = sh.prow + (k & 1) * kWave + base;
       if (r == idx) {
@@ -598,14 +601,14 @@ __device__ __forceinline__ void factor_newton_matrix(const Shared& sh, const dou
         pos = k;
         sh.perm[base + k] = r;
 #pragma unroll
-        for (int c = k; c < NP; ++c) prow[c] = a[c];
+        for (int c = k; c < NC; ++c) prow[c] = a[c];
       }
       wave_sync();
       if (!used) {
         const double l = a[k] / prow[k];
         a[k] = l;
 #pragma unroll
-        for (int c = k + 1; c < NP; ++c) a[c] -= l * prow[c];
+        for (int c = k + 1; c < NC; ++c) a[c] -= l * prow[c];
       }
     }
   }
@@ -615,15 +618,16 @@ __device__ __forceinline__ void factor_newton_matrix(const Shared& sh, const dou
   // identity and are not stored.
   if (pos >= 0 && pos < sh.rows) {
 #pragma unroll
-    for (int c = 0; c < NP; ++c) Jg[pos * sh.ldj + c] = a[c];
+    for (int c = 0; c < NC; ++c) Jg[pos * sh.ldj + c] = a[c];
   }
+  if (r >= NC) sh.perm[base + r] = r;   // padding lanes past NC keep their own position
   wave_sync();
   rdiag = r < sh.rows ? 1.0 / Jg[r * sh.ldj + r] : 1.0;
 }
 
 // Solve M x = b with the pivot-ordered factors; lane r holds b_r (component
 // r) on entry and returns x_r.
-template <int NP>
+template <int NP, int NC = NP>
 __device__ __forceinline__ double lu_solve(const Shared& sh, const double rdiag, const double b) {
   const int lane = opaque_lane();
   const int r = lane % NP;
@@ -631,13 +635,13 @@ __device__ __forceinline__ double lu_solve(const Shared& sh, const double rdiag,
   const double* Jg = sh.J + (size_t)(lane / NP) * sh.rows * sh.ldj;
   double z = __shfl(b, base + sh.perm[base + r]);   // b in pivot order
 #pragma unroll
-  for (int k = 0; k < NP - 1; ++k) {
+  for (int k = 0; k < NC - 1; ++k) {
     const double zk = gbcast<NP>(z, k);
     if (r > k && r < sh.rows) z -= Jg[r * sh.ldj + k] * zk;
   }
   double x = 0.0;
 #pragma unroll
-  for (int k = NP - 1; k >= 0; --k) {
+  for (int k = NC - 1; k >= 0; --k) {
     const double xk = gbcast<NP>(z * rdiag, k);
     if (r < k && r < sh.rows) z -= Jg[r * sh.ldj + k] * xk;
     if (r == k) x = xk;
@@ -875,7 +879,7 @@ __device__ __forceinline__ void init_shared_constants(const DevMech& m, const Sh
 // own equation).
 // One group integrates cell `cell` of the SoA arrays (Tg, Yg, n) over [0, dt];
 // its record goes to column rec_cell of the rec array with rec_n columns.
-template <int NP, bool F32>
+template <int NP, bool F32, int NC = NP>
 __device__ __forceinline__ void integrate_group(const DevMech& m, const IntParams& P, const double dt,
                                                 const Shared& sh, const Spc& sc, double* __restrict__ Tg,
                                                 double* __restrict__ Yg, const int64_t n, const int64_t cell,
@@ -978,7 +982,7 @@ __device__ __forceinline__ void integrate_group(const DevMech& m, const IntParam
         }
         njac++;
         if constexpr (F32) factor_newton_matrix_f32<NP>(sh, c, rdiag32);
-        else factor_newton_matrix<NP>(sh, c, rdiag);
+        else factor_newton_matrix<NP, NC>(sh, c, rdiag);
         have_lu = true;
         c_lu = c;
         steps_lu = steps;
@@ -1002,7 +1006,7 @@ __device__ __forceinline__ void integrate_group(const DevMech& m, const IntParam
         const double b = (rl < N) ? -(d - c * fi + psi) : 0.0;
         double delta;
         if constexpr (F32) delta = solve_refined<NP>(sh, rdiag32, c, b, w, N, P.ir_max, nir);
-        else delta = lu_solve<NP>(sh, rdiag, b);
+        else delta = lu_solve<NP, NC>(sh, rdiag, b);
         d += delta;
         const double nrm = wrms<NP>(delta, w, N);
         if (nrm <= ntol) {
@@ -1131,7 +1135,7 @@ __device__ __forceinline__ void integrate_group(const DevMech& m, const IntParam
   }
 }
 
-template <int NP, bool F32>
+template <int NP, bool F32, int NC = NP>
 __global__ __launch_bounds__(kWave) void integrate_kernel(const DevMech m, const IntParams P, double* __restrict__ Tg,
                                                           double* __restrict__ Yg, const int64_t n,
                                                           int32_t* __restrict__ rec) {
@@ -1143,7 +1147,7 @@ __global__ __launch_bounds__(kWave) void integrate_kernel(const DevMech m, const
   if (cell >= n) return;   // whole groups leave together
   init_shared_constants<NP>(m, sh);
   const Spc sc = load_species(m, r);
-  integrate_group<NP, F32>(m, P, P.dt, sh, sc, Tg, Yg, n, cell, rec, n, cell);
+  integrate_group<NP, F32, NC>(m, P, P.dt, sh, sc, Tg, Yg, n, cell, rec, n, cell);
 }
 
 // Persistent variant for many boxes of uneven size and step: each wave takes
@@ -1151,7 +1155,7 @@ __global__ __launch_bounds__(kWave) void integrate_kernel(const DevMech m, const
 // empty.  Items follow the box order given by the host (largest boxes first);
 // the wave that finishes a box's last tile raises that box's flag in
 // host-mapped memory (for latency timing on the host).
-template <int NP, bool F32>
+template <int NP, bool F32, int NC = NP>
 __global__ __launch_bounds__(kWave) void boxes_kernel(const DevMech m, const IntParams P,
                                                       const BoxDev* __restrict__ boxes, const BoxJob* __restrict__ job,
                                                       unsigned* __restrict__ head, int* __restrict__ remaining,
@@ -1185,7 +1189,7 @@ __global__ __launch_bounds__(kWave) void boxes_kernel(const DevMech m, const Int
     }
     const BoxDev bx = boxes[lo];
     const int64_t c = ((int64_t)item - bx.tile_pre) * (kWave / NP) + g;
-    if (c < bx.n) integrate_group<NP, F32>(m, P, bx.dt, sh, sc, bx.T, bx.Y, bx.n, c, rec, rec_n, bx.cell_off + c);
+    if (c < bx.n) integrate_group<NP, F32, NC>(m, P, bx.dt, sh, sc, bx.T, bx.Y, bx.n, c, rec, rec_n, bx.cell_off + c);
     if (opaque_lane() == 0) {
       const int left = atomicSub(&remaining[lo], 1);
       if (left == 1 && host_done != nullptr) {
@@ -1259,7 +1263,7 @@ __device__ __forceinline__ uint64_t load_sys_u64(const void* p) {
   return __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-template <int NP, bool F32>
+template <int NP, bool F32, int NC = NP>
 __global__ __launch_bounds__(kWave) void serve_kernel(const DevMech m, const IntParams P, const ServeQueue q) {
   extern __shared__ double smem[];
   const Shared sh = carve(smem, NP, m.N, F32);
@@ -1292,7 +1296,7 @@ __global__ __launch_bounds__(kWave) void serve_kernel(const DevMech m, const Int
     bx.dt = __builtin_bit_cast(double, bcast_u64(w[4]));
     bx.tile_pre = (int64_t)bcast_u64(w[5]);
     const int64_t c = ((int64_t)item - bx.tile_pre) * kCpt + g;
-    if (c < bx.n) integrate_group<NP, F32>(m, P, bx.dt, sh, sc, bx.T, bx.Y, bx.n, c, bx.rec, bx.n, c);
+    if (c < bx.n) integrate_group<NP, F32, NC>(m, P, bx.dt, sh, sc, bx.T, bx.Y, bx.n, c, bx.rec, bx.n, c);
     __syncthreads();
     if (lane == 0) serve_finish(q, slot, (int)((bx.n + kCpt - 1) / kCpt));
     if (q.quantum > 0 && (int64_t)(__builtin_amdgcn_s_memrealtime() - t0) > q.quantum) break;
@@ -1395,6 +1399,11 @@ __global__ void zero_u64_kernel(unsigned long long* p, int cnt) {
   if (i < cnt) p[i] = 0;
 }
 
+// Columns carried by the FP64 factorisation of the 64-lane kernels when the
+// cell's N fits (S up to 55): eight padding columns fewer to eliminate and
+// solve.  Larger mechanisms take all 64.
+constexpr int kNarrowCols = 56;
+
 template <int NP>
 hipError_t launch_integrate_np(const DevMech& m, const IntParams& prm, double* T, double* Y, int64_t n,
                                int32_t* rec, hipStream_t stream) {
@@ -1402,6 +1411,13 @@ hipError_t launch_integrate_np(const DevMech& m, const IntParams& prm, double* T
   const int64_t blocks = (n + cpw - 1) / cpw;
   const bool f32 = prm.lu_fp32 != 0;
   const size_t lds = integrate_lds_bytes(NP, m.N, f32);
+  if constexpr (NP == kWave) {
+    if (!f32 && m.N <= kNarrowCols) {
+      hipLaunchKernelGGL((integrate_kernel<NP, false, kNarrowCols>), dim3((unsigned)blocks), dim3(kWave), lds,
+                         stream, m, prm, T, Y, n, rec);
+      return hipGetLastError();
+    }
+  }
   if (f32)
     hipLaunchKernelGGL((integrate_kernel<NP, true>), dim3((unsigned)blocks), dim3(kWave), lds, stream, m, prm, T, Y,
                        n, rec);
@@ -1429,6 +1445,13 @@ hipError_t launch_boxes_np(const DevMech& m, const IntParams& prm, const BoxDev*
   const bool f32 = prm.lu_fp32 != 0;
   const size_t lds = integrate_lds_bytes(NP, m.N, f32);
   hipLaunchKernelGGL(boxes_init_kernel, dim3(64), dim3(256), 0, stream, boxes, job, head, remaining);
+  if constexpr (NP == kWave) {
+    if (!f32 && m.N <= kNarrowCols) {
+      hipLaunchKernelGGL((boxes_kernel<NP, false, kNarrowCols>), dim3(grid), dim3(kWave), lds, stream, m, prm, boxes,
+                         job, head, remaining, rec, host_done);
+      return hipGetLastError();
+    }
+  }
   if (f32)
     hipLaunchKernelGGL((boxes_kernel<NP, true>), dim3(grid), dim3(kWave), lds, stream, m, prm, boxes, job, head,
                        remaining, rec, host_done);
@@ -1442,6 +1465,12 @@ template <int NP>
 hipError_t launch_serve_np(const DevMech& m, const IntParams& prm, const ServeQueue& q, int grid, hipStream_t stream) {
   const bool f32 = prm.lu_fp32 != 0;
   const size_t lds = integrate_lds_bytes(NP, m.N, f32);
+  if constexpr (NP == kWave) {
+    if (!f32 && m.N <= kNarrowCols) {
+      hipLaunchKernelGGL((serve_kernel<NP, false, kNarrowCols>), dim3(grid), dim3(kWave), lds, stream, m, prm, q);
+      return hipGetLastError();
+    }
+  }
   if (f32)
     hipLaunchKernelGGL((serve_kernel<NP, true>), dim3(grid), dim3(kWave), lds, stream, m, prm, q);
   else
@@ -1453,6 +1482,13 @@ template <int NP>
 int serve_waves_np(const DevMech& m, bool f32) {
   int blocks = 0;
   const size_t lds = integrate_lds_bytes(NP, m.N, f32);
+  if constexpr (NP == kWave) {
+    if (!f32 && m.N <= kNarrowCols) {
+      const hipError_t e =
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, serve_kernel<NP, false, kNarrowCols>, kWave, lds);
+      return e == hipSuccess && blocks > 0 ? blocks : 1;
+    }
+  }
   const hipError_t e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, serve_kernel<NP, true>, kWave, lds)
                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, serve_kernel<NP, false>, kWave, lds);
   return e == hipSuccess && blocks > 0 ? blocks : 1;
