@@ -323,6 +323,19 @@ def test_determinism(chem, torch_dev, kernel):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[3], b[3])
 
 
+def test_determinism_53_species(chem, torch_dev):
+    """The 64-lane group kernel (53 species, production rates and Jacobian
+    added into LDS by the reaction lanes with atomics) repeats bit for bit."""
+    w = synth.config_workload(3, GOLDEN, shape=(256, 1, 1))
+    idx = np.arange(0, 256, 4)
+    text = w.mech.to_text()
+    say(f"determinism 53 species n={idx.size}")
+    a = gpu_integrate(chem, torch_dev, text, w.T[idx], w.Y[:, idx], w.p, w.dt, w.rtol, w.atol)
+    b = gpu_integrate(chem, torch_dev, text, w.T[idx], w.Y[:, idx], w.p, w.dt, w.rtol, w.atol)
+    assert a[2]["rc"] == 0 and (a[3][0] == 0).all()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[3], b[3])
+
+
 def test_config4_mechanism_sample(chem, torch_dev):
     m = synth.config_mechanism(4)
     boxes = synth.amr_boxes(m, 6, synth.config_seed(4), max_cells=24)
