@@ -303,7 +303,8 @@ def kernel_name(args, N):
     if lane:
         return "chem_lpc_integrate (generated for the mechanism, hipRTC)"
     np_ = 16 if N <= 16 else (32 if N <= 32 else 64)
-    return f"integrate_kernel<{np_}, {'true' if args.lu_fp32 else 'false'}>"
+    cols = 56 if (np_ == 64 and N <= 56) else np_       # columns the 64-lane factorisations carry
+    return f"integrate_kernel<{np_}, {'true' if args.lu_fp32 else 'false'}, {cols}>"
 
 
 def cpu_baseline(w, Tg, Yg, args, worst=None):

@@ -706,21 +706,21 @@ __device__ __forceinline__ int jac_difference_quotients(const DevMech& m, const 
 // Mixed-precision option: the same pivoted factorisation of M = I - c J in
 // FP32 (M rounded from FP64), factors kept in FP32 LDS rows in pivot order;
 // J stays in FP64 for the refinement residuals.
-template <int NP>
+template <int NP, int NC = NP>
 __device__ __forceinline__ void factor_newton_matrix_f32(const Shared& sh, const double cfac, float& rdiag) {
   const int lane = opaque_lane();
   const int r = lane % NP;
   const int base = lane - r;
   const double* Jg = sh.J + (size_t)(lane / NP) * sh.rows * sh.ldj;
   float* Fg = sh.F + (size_t)(lane / NP) * sh.rows * sh.ldj;
-  float a[NP];
+  float a[NC];
 #pragma unroll
-  for (int c = 0; c < NP; ++c)
+  for (int c = 0; c < NC; ++c)
     a[c] = (float)(((c == r) ? 1.0 : 0.0) - (r < sh.rows ? cfac * Jg[r * sh.ldj + c] : 0.0));
   bool used = false;
   int pos = -1;
 #pragma unroll
-  for (int k = 0; k < NP; ++k) {
+  for (int k = 0; k < NC; ++k) {
     double cand = used ? -1.0 : (double)fabsf(a[k]);
     if (!(cand == cand)) cand = -1.0;
     const int idx = gpivot<NP>(cand);
@@ -734,7 +734,7 @@ __device__ __forceinline__ void factor_newton_matrix_f32(const Shared& sh, const
       const float l = used ? 0.0f : a[k] / pk;
       if (!used) a[k] = l;
 #pragma unroll
-      for (int c = k + 1; c < NP; ++c) a[c] -= l * readlane_f(a[c], idx);
+      for (int c = k + 1; c < NC; ++c) a[c] -= l * readlane_f(a[c], idx);
     } else {
       float* prow = sh.prow32 + (k & 1) * kWave + base;
       if (r == idx) {
@@ -742,26 +742,27 @@ __device__ __forceinline__ void factor_newton_matrix_f32(const Shared& sh, const
         pos = k;
         sh.perm[base + k] = r;
 #pragma unroll
-        for (int c = k; c < NP; ++c) prow[c] = a[c];
+        for (int c = k; c < NC; ++c) prow[c] = a[c];
       }
       wave_sync();
       if (!used) {
         const float l = a[k] / prow[k];
         a[k] = l;
 #pragma unroll
-        for (int c = k + 1; c < NP; ++c) a[c] -= l * prow[c];
+        for (int c = k + 1; c < NC; ++c) a[c] -= l * prow[c];
       }
     }
   }
   if (pos >= 0 && pos < sh.rows) {
 #pragma unroll
-    for (int c = 0; c < NP; ++c) Fg[pos * sh.ldj + c] = a[c];
+    for (int c = 0; c < NC; ++c) Fg[pos * sh.ldj + c] = a[c];
   }
+  if (r >= NC) sh.perm[base + r] = r;   // padding lanes past NC keep their own position
   wave_sync();
   rdiag = r < sh.rows ? 1.0f / Fg[r * sh.ldj + r] : 1.0f;
 }
 
-template <int NP>
+template <int NP, int NC = NP>
 __device__ __forceinline__ double lu_solve_f32(const Shared& sh, const float rdiag, const double b) {
   const int lane = opaque_lane();
   const int r = lane % NP;
@@ -769,13 +770,13 @@ __device__ __forceinline__ double lu_solve_f32(const Shared& sh, const float rdi
   const float* Fg = sh.F + (size_t)(lane / NP) * sh.rows * sh.ldj;
   float z = (float)__shfl(b, base + sh.perm[base + r]);
 #pragma unroll
-  for (int k = 0; k < NP - 1; ++k) {
+  for (int k = 0; k < NC - 1; ++k) {
     const float zk = gbcastf<NP>(z, k);
     if (r > k && r < sh.rows) z -= Fg[r * sh.ldj + k] * zk;
   }
   float x = 0.0f;
 #pragma unroll
-  for (int k = NP - 1; k >= 0; --k) {
+  for (int k = NC - 1; k >= 0; --k) {
     const float xk = gbcastf<NP>(z * rdiag, k);
     if (r < k && r < sh.rows) z -= Fg[r * sh.ldj + k] * xk;
     if (r == k) x = xk;
@@ -787,19 +788,19 @@ __device__ __forceinline__ double lu_solve_f32(const Shared& sh, const float rdi
 // refinement sweeps x += LU32^-1 (b - M x) with the residual in FP64
 // (M x = x - c J x from the FP64 Jacobian rows), until the WRMS correction is
 // below 1e-8 or ir_max sweeps have run.
-template <int NP>
+template <int NP, int NC = NP>
 __device__ __forceinline__ double solve_refined(const Shared& sh, const float rdiag, const double cfac, const double b,
                                                 const double w, const int N, const int ir_max, int& sweeps) {
   const int lane = opaque_lane();
   const int r = lane % NP;
   const double* Jg = sh.J + (size_t)(lane / NP) * sh.rows * sh.ldj;
-  double x = lu_solve_f32<NP>(sh, rdiag, b);
+  double x = lu_solve_f32<NP, NC>(sh, rdiag, b);
   for (int s = 0; s < ir_max; ++s) {
     double jx = 0.0;
 #pragma unroll
-    for (int c = 0; c < NP; ++c) jx += (r < sh.rows ? Jg[r * sh.ldj + c] : 0.0) * gbcast<NP>(x, c);
+    for (int c = 0; c < NC; ++c) jx += (r < sh.rows ? Jg[r * sh.ldj + c] : 0.0) * gbcast<NP>(x, c);
     const double res = b - (x - cfac * jx);
-    const double dx = lu_solve_f32<NP>(sh, rdiag, res);
+    const double dx = lu_solve_f32<NP, NC>(sh, rdiag, res);
     x += dx;
     sweeps++;
     if (wrms<NP>(dx, w, N) <= 1e-8) break;
@@ -981,7 +982,7 @@ __device__ __forceinline__ void integrate_group(const DevMech& m, const IntParam
             nrhs += jac_difference_quotients<NP>(m, sc, P.p, fixedT, pred, fp, w, h, N, N - 1, sh);
         }
         njac++;
-        if constexpr (F32) factor_newton_matrix_f32<NP>(sh, c, rdiag32);
+        if constexpr (F32) factor_newton_matrix_f32<NP, NC>(sh, c, rdiag32);
         else factor_newton_matrix<NP, NC>(sh, c, rdiag);
         have_lu = true;
         c_lu = c;
@@ -1005,7 +1006,7 @@ __device__ __forceinline__ void integrate_group(const DevMech& m, const IntParam
         nnewton++;
         const double b = (rl < N) ? -(d - c * fi + psi) : 0.0;
         double delta;
-        if constexpr (F32) delta = solve_refined<NP>(sh, rdiag32, c, b, w, N, P.ir_max, nir);
+        if constexpr (F32) delta = solve_refined<NP, NC>(sh, rdiag32, c, b, w, N, P.ir_max, nir);
         else delta = lu_solve<NP, NC>(sh, rdiag, b);
         d += delta;
         const double nrm = wrms<NP>(delta, w, N);
@@ -1399,9 +1400,9 @@ __global__ void zero_u64_kernel(unsigned long long* p, int cnt) {
   if (i < cnt) p[i] = 0;
 }
 
-// Columns carried by the FP64 factorisation of the 64-lane kernels when the
-// cell's N fits (S up to 55): eight padding columns fewer to eliminate and
-// solve.  Larger mechanisms take all 64.
+// Columns carried by the factorisations (FP64 and FP32) of the 64-lane
+// kernels when the cell's N fits (S up to 55): eight padding columns fewer to
+// eliminate, solve and refine.  Larger mechanisms take all 64.
 constexpr int kNarrowCols = 56;
 
 template <int NP>
@@ -1412,9 +1413,13 @@ hipError_t launch_integrate_np(const DevMech& m, const IntParams& prm, double* T
   const bool f32 = prm.lu_fp32 != 0;
   const size_t lds = integrate_lds_bytes(NP, m.N, f32);
   if constexpr (NP == kWave) {
-    if (!f32 && m.N <= kNarrowCols) {
-      hipLaunchKernelGGL((integrate_kernel<NP, false, kNarrowCols>), dim3((unsigned)blocks), dim3(kWave), lds,
-                         stream, m, prm, T, Y, n, rec);
+    if (m.N <= kNarrowCols) {
+      if (f32)
+        hipLaunchKernelGGL((integrate_kernel<NP, true, kNarrowCols>), dim3((unsigned)blocks), dim3(kWave), lds,
+                           stream, m, prm, T, Y, n, rec);
+      else
+        hipLaunchKernelGGL((integrate_kernel<NP, false, kNarrowCols>), dim3((unsigned)blocks), dim3(kWave), lds,
+                           stream, m, prm, T, Y, n, rec);
       return hipGetLastError();
     }
   }
@@ -1446,9 +1451,13 @@ hipError_t launch_boxes_np(const DevMech& m, const IntParams& prm, const BoxDev*
   const size_t lds = integrate_lds_bytes(NP, m.N, f32);
   hipLaunchKernelGGL(boxes_init_kernel, dim3(64), dim3(256), 0, stream, boxes, job, head, remaining);
   if constexpr (NP == kWave) {
-    if (!f32 && m.N <= kNarrowCols) {
-      hipLaunchKernelGGL((boxes_kernel<NP, false, kNarrowCols>), dim3(grid), dim3(kWave), lds, stream, m, prm, boxes,
-                         job, head, remaining, rec, host_done);
+    if (m.N <= kNarrowCols) {
+      if (f32)
+        hipLaunchKernelGGL((boxes_kernel<NP, true, kNarrowCols>), dim3(grid), dim3(kWave), lds, stream, m, prm,
+                           boxes, job, head, remaining, rec, host_done);
+      else
+        hipLaunchKernelGGL((boxes_kernel<NP, false, kNarrowCols>), dim3(grid), dim3(kWave), lds, stream, m, prm,
+                           boxes, job, head, remaining, rec, host_done);
       return hipGetLastError();
     }
   }
@@ -1466,8 +1475,11 @@ hipError_t launch_serve_np(const DevMech& m, const IntParams& prm, const ServeQu
   const bool f32 = prm.lu_fp32 != 0;
   const size_t lds = integrate_lds_bytes(NP, m.N, f32);
   if constexpr (NP == kWave) {
-    if (!f32 && m.N <= kNarrowCols) {
-      hipLaunchKernelGGL((serve_kernel<NP, false, kNarrowCols>), dim3(grid), dim3(kWave), lds, stream, m, prm, q);
+    if (m.N <= kNarrowCols) {
+      if (f32)
+        hipLaunchKernelGGL((serve_kernel<NP, true, kNarrowCols>), dim3(grid), dim3(kWave), lds, stream, m, prm, q);
+      else
+        hipLaunchKernelGGL((serve_kernel<NP, false, kNarrowCols>), dim3(grid), dim3(kWave), lds, stream, m, prm, q);
       return hipGetLastError();
     }
   }
@@ -1483,9 +1495,10 @@ int serve_waves_np(const DevMech& m, bool f32) {
   int blocks = 0;
   const size_t lds = integrate_lds_bytes(NP, m.N, f32);
   if constexpr (NP == kWave) {
-    if (!f32 && m.N <= kNarrowCols) {
+    if (m.N <= kNarrowCols) {
       const hipError_t e =
-          hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, serve_kernel<NP, false, kNarrowCols>, kWave, lds);
+          f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, serve_kernel<NP, true, kNarrowCols>, kWave, lds)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, serve_kernel<NP, false, kNarrowCols>, kWave, lds);
       return e == hipSuccess && blocks > 0 ? blocks : 1;
     }
   }
