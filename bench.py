@@ -89,6 +89,9 @@ def main():
                          "sweep: error against the tight-tolerance truth and cost over rtol x dt; "
                          "peak: the FP64 FMA rate and the cost of one exp on this device (probe kernels)")
     ap.add_argument("--lu-fp32", action="store_true", help="FP32 Newton-matrix LU with FP64 refinement")
+    ap.add_argument("--ir-max", type=int, default=3,
+                    help="with --lu-fp32: refinement sweeps per Newton solve at most (0 = the FP32 solve alone; "
+                         "Newton's own FP64 residual then corrects it)")
     ap.add_argument("--jac-reuse", action="store_true",
                     help="keep the factored Newton matrix across attempts while it is recent (CVODE's policy); "
                          "default: a fresh Jacobian and LU every attempt")
@@ -141,7 +144,7 @@ def main():
     gm = chem.Mechanism(m.to_text())
     load_ms = (time.perf_counter() - t_load) * 1e3
     gm.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32), kernel=KERNEL_CODES[args.kernel],
-                   jac_reuse=int(args.jac_reuse))
+                   jac_reuse=int(args.jac_reuse), ir_max=args.ir_max)
     kname = kernel_name(args, m.n_species + 1)
     T0 = torch.tensor(w.T, dtype=torch.float64, device=dev)
     Y0 = torch.tensor(w.Y, dtype=torch.float64, device=dev)
@@ -219,7 +222,10 @@ def main():
                              "(lane-per-cell family) and is not timed in value"},
         "integration": {"steps_per_cell": st["n_steps_total"] / n, "attempts_per_cell": st["n_attempts"] / n,
                         "newton_per_cell": st["n_newton_iters"] / n, "max_steps_cell": st["n_steps_max"],
-                        "failed_cells": st["n_cells_failed"]},
+                        "failed_cells": st["n_cells_failed"],
+                        "refinement_sweeps_per_newton": (st["n_ir_sweeps"] / max(st["n_newton_iters"], 1)
+                                                         if args.lu_fp32 else None),
+                        "ir_max": args.ir_max if args.lu_fp32 else None},
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
