@@ -151,7 +151,7 @@ hipError_t launch_boxes(const DevMech& m, const IntParams& prm, const BoxDev* bo
 hipError_t launch_reduce_records(const int32_t* rec, int64_t n, unsigned long long* out, hipStream_t stream);
 hipError_t launch_reduce_records_job(const int32_t* rec, const BoxJob* job, unsigned long long* out,
                                      hipStream_t stream);
-size_t integrate_lds_bytes(int np_width, int N, bool f32);
+size_t integrate_lds_bytes(int np_width, int N, bool f32, bool f32_in_place = false);
 hipError_t launch_boxes_init(const BoxDev* boxes, const BoxJob* job, unsigned* head, int* remaining,
                              hipStream_t stream);
 // Resident serving kernel of the group family on `grid` waves, and the

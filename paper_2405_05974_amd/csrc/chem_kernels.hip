@@ -215,7 +215,11 @@ struct Shared {
   int rows;       // stored matrix rows per group: N; rows N..NP-1 are identity and not stored
 };
 
-__device__ __forceinline__ Shared carve(double* smem, int NP, int N, bool f32 = false) {
+// With f32_in_place (FP32 LU without refinement sweeps, one group per wave)
+// the FP32 factors overwrite the group's FP64 Jacobian rows, which nothing
+// reads after the factorisation then, and the LDS per wave stays that of the
+// FP64 path.
+__device__ __forceinline__ Shared carve(double* smem, int NP, int N, bool f32 = false, bool f32_in_place = false) {
   Shared s;
   s.ldj = NP + 1;
   s.rows = N;
@@ -230,18 +234,23 @@ __device__ __forceinline__ Shared carve(double* smem, int NP, int N, bool f32 = 
   s.perm = reinterpret_cast<int*>(s.prow + 2 * kWave);
   s.J = s.prow + 2 * kWave + kWave / 2;   // perm takes 64 ints = 32 doubles
   const size_t jd = (size_t)(kWave / NP) * N * (NP + 1);
-  s.F = f32 ? reinterpret_cast<float*>(s.J + jd) : nullptr;
-  s.prow32 = f32 ? s.F + jd : nullptr;
+  if (f32 && f32_in_place) {
+    s.F = reinterpret_cast<float*>(s.J);
+    s.prow32 = reinterpret_cast<float*>(s.prow);   // unused: the 64-lane pivot row goes by readlane
+  } else {
+    s.F = f32 ? reinterpret_cast<float*>(s.J + jd) : nullptr;
+    s.prow32 = f32 ? s.F + jd : nullptr;
+  }
   return s;
 }
 
 }  // namespace
 
-size_t integrate_lds_bytes(int np_width, int N, bool f32) {
+size_t integrate_lds_bytes(int np_width, int N, bool f32, bool f32_in_place) {
   const int groups = kWave / np_width;
   const size_t jd = (size_t)groups * N * (np_width + 1);
   const size_t doubles = 6 * kWave + 3 * kWave + 2 * kWave + kWave / 2 + jd;
-  return doubles * sizeof(double) + (f32 ? (jd + 2 * kWave) * sizeof(float) : 0);
+  return doubles * sizeof(double) + (f32 && !f32_in_place ? (jd + 2 * kWave) * sizeof(float) : 0);
 }
 
 namespace {
@@ -753,6 +762,9 @@ __device__ __forceinline__ void factor_newton_matrix_f32(const Shared& sh, const
       }
     }
   }
+  // every lane's FP64 row has been read before any FP32 row is stored (the
+  // factors may overwrite the FP64 rows, see carve)
+  wave_sync();
   if (pos >= 0 && pos < sh.rows) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) Fg[pos * sh.ldj + c] = a[c];
@@ -1141,7 +1153,7 @@ __global__ __launch_bounds__(kWave) void integrate_kernel(const DevMech m, const
                                                           double* __restrict__ Yg, const int64_t n,
                                                           int32_t* __restrict__ rec) {
   extern __shared__ double smem[];
-  const Shared sh = carve(smem, NP, m.N, F32);
+  const Shared sh = carve(smem, NP, m.N, F32, F32 && NP == kWave && P.ir_max == 0);
   const int lane = threadIdx.x & (kWave - 1);
   const int r = lane % NP;
   const int64_t cell = (int64_t)blockIdx.x * (kWave / NP) + lane / NP;
@@ -1162,7 +1174,7 @@ __global__ __launch_bounds__(kWave) void boxes_kernel(const DevMech m, const Int
                                                       unsigned* __restrict__ head, int* __restrict__ remaining,
                                                       int32_t* __restrict__ rec, int* __restrict__ host_done) {
   extern __shared__ double smem[];
-  const Shared sh = carve(smem, NP, m.N, F32);
+  const Shared sh = carve(smem, NP, m.N, F32, F32 && NP == kWave && P.ir_max == 0);
   const int lane = threadIdx.x & (kWave - 1);
   const int r = lane % NP;
   const int g = lane / NP;
@@ -1267,7 +1279,7 @@ __device__ __forceinline__ uint64_t load_sys_u64(const void* p) {
 template <int NP, bool F32, int NC = NP>
 __global__ __launch_bounds__(kWave) void serve_kernel(const DevMech m, const IntParams P, const ServeQueue q) {
   extern __shared__ double smem[];
-  const Shared sh = carve(smem, NP, m.N, F32);
+  const Shared sh = carve(smem, NP, m.N, F32, F32 && NP == kWave && P.ir_max == 0);
   const int lane = threadIdx.x & (kWave - 1);
   const int r = lane % NP;
   const int g = lane / NP;
@@ -1411,7 +1423,7 @@ hipError_t launch_integrate_np(const DevMech& m, const IntParams& prm, double* T
   const int cpw = kWave / NP;
   const int64_t blocks = (n + cpw - 1) / cpw;
   const bool f32 = prm.lu_fp32 != 0;
-  const size_t lds = integrate_lds_bytes(NP, m.N, f32);
+  const size_t lds = integrate_lds_bytes(NP, m.N, f32, f32 && NP == kWave && prm.ir_max == 0);
   if constexpr (NP == kWave) {
     if (m.N <= kNarrowCols) {
       if (f32)
@@ -1448,7 +1460,7 @@ hipError_t launch_boxes_np(const DevMech& m, const IntParams& prm, const BoxDev*
                            unsigned* head, int* remaining, int32_t* rec, int* host_done, int grid,
                            hipStream_t stream) {
   const bool f32 = prm.lu_fp32 != 0;
-  const size_t lds = integrate_lds_bytes(NP, m.N, f32);
+  const size_t lds = integrate_lds_bytes(NP, m.N, f32, f32 && NP == kWave && prm.ir_max == 0);
   hipLaunchKernelGGL(boxes_init_kernel, dim3(64), dim3(256), 0, stream, boxes, job, head, remaining);
   if constexpr (NP == kWave) {
     if (m.N <= kNarrowCols) {
@@ -1473,7 +1485,7 @@ hipError_t launch_boxes_np(const DevMech& m, const IntParams& prm, const BoxDev*
 template <int NP>
 hipError_t launch_serve_np(const DevMech& m, const IntParams& prm, const ServeQueue& q, int grid, hipStream_t stream) {
   const bool f32 = prm.lu_fp32 != 0;
-  const size_t lds = integrate_lds_bytes(NP, m.N, f32);
+  const size_t lds = integrate_lds_bytes(NP, m.N, f32, f32 && NP == kWave && prm.ir_max == 0);
   if constexpr (NP == kWave) {
     if (m.N <= kNarrowCols) {
       if (f32)
@@ -1490,6 +1502,8 @@ hipError_t launch_serve_np(const DevMech& m, const IntParams& prm, const ServeQu
   return hipGetLastError();
 }
 
+// (sized with the FP32 rows kept apart from the FP64 ones: an upper bound of
+// the LDS the launch takes)
 template <int NP>
 int serve_waves_np(const DevMech& m, bool f32) {
   int blocks = 0;

@@ -730,6 +730,53 @@ def test_fp32_lu_with_kept_matrices(chem, torch_dev):
     assert np.abs(Yg - Yt).max() <= barY and (np.abs(Tg - Tt) / Tt).max() <= barT
 
 
+def test_fp32_lu_without_refinement(chem, torch_dev):
+    """The FP32-LU option with no refinement sweeps (ir_max 0: Newton's own
+    FP64 residual corrects the FP32 solve).  At 64 lanes per cell the FP32
+    factors then overwrite the FP64 Jacobian rows in LDS.  Config-3 flame
+    cells (64 lanes) and config-1 cells (16 lanes, rows kept apart) against
+    the FP64 oracle at the option's 1e-6 bar; config-3 cells with the factors
+    kept across attempts against the oracle's kept-matrix option and the
+    truth, with the bar derived in test_fp32_lu_with_kept_matrices."""
+    import oracle
+    w3 = synth.config_workload(3, GOLDEN, shape=(256, 1, 1))
+    idx = np.arange(0, 256, 16)
+    text3 = w3.mech.to_text()
+    for what, text, T, Y, p, dt, rtol in (
+            ("config3 flame (64 lanes, factors in place)", text3, w3.T[idx], w3.Y[:, idx], w3.p, w3.dt, w3.rtol),
+            ("config1 (16 lanes)", None, None, None, None, 2e-6, 1e-6)):
+        if text is None:
+            w1 = synth.config_workload(1, n=128)
+            text, T, Y, p = w1.mech.to_text(), w1.T, w1.Y, w1.p
+        say(f"lu_fp32 ir_max 0: {what} n={T.size}")
+        Tg, Yg, st, rec = gpu_integrate(chem, torch_dev, text, T, Y, p, dt, rtol, 1e-12, lu_fp32=1, ir_max=0)
+        assert st["rc"] == 0 and st["n_ir_sweeps"] == 0 and (rec[0] == 0).all()
+        To, Yo, so = oracle_integrate(text, T, Y, p, dt, rtol, 1e-12)
+        dY = np.abs(Yg - Yo).max()
+        dT = (np.abs(Tg - To) / To).max()
+        say(f"lu_fp32 ir_max 0: {what} vs FP64 oracle max|dY|={dY:.3e} max|dT|/T={dT:.3e}")
+        assert dY <= TOL_F32 and dT <= TOL_F32, what
+    kdx = np.arange(0, 256, 32)
+    T, Y = w3.T[kdx], w3.Y[:, kdx]
+    say(f"lu_fp32 ir_max 0 + jac_reuse: config3 flame n={kdx.size}")
+    Tg, Yg, st, rec = gpu_integrate(chem, torch_dev, text3, T, Y, w3.p, w3.dt, w3.rtol, w3.atol, lu_fp32=1, ir_max=0,
+                                    jac_reuse=1)
+    assert st["rc"] == 0 and (rec[0] == 0).all() and st["n_jac"] < 0.5 * st["n_attempts"]
+    say("lu_fp32 ir_max 0 + jac_reuse: oracle kept option and truth")
+    To, Yo, _ = oracle_integrate(text3, T, Y, w3.p, w3.dt, w3.rtol, w3.atol, jac_reuse=True)
+    Tt, Yt, _ = oracle.Mech(text3).integrate(T, Y, w3.p, w3.dt, 1e-12, 1e-20)
+    eY = np.abs(Yo - Yt).max()
+    eT = (np.abs(To - Tt) / Tt).max()
+    barY = 2.0 * max(1e-6, eY)
+    barT = 2.0 * max(1e-6, eT)
+    dY = np.abs(Yg - Yo).max()
+    dT = (np.abs(Tg - To) / To).max()
+    say(f"lu_fp32 ir_max 0 kept: vs oracle kept {dY:.3e} / {dT:.3e}; oracle kept vs truth {eY:.3e} / {eT:.3e}; "
+        f"GPU vs truth {np.abs(Yg - Yt).max():.3e} / {(np.abs(Tg - Tt) / Tt).max():.3e}")
+    assert dY <= barY and dT <= barT
+    assert np.abs(Yg - Yt).max() <= barY and (np.abs(Tg - Tt) / Tt).max() <= barT
+
+
 # ------------------------------------------------------------------ serving
 
 @pytest.mark.parametrize("streams", [1, 3])
