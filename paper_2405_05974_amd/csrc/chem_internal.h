@@ -157,7 +157,7 @@ hipError_t launch_boxes_init(const BoxDev* boxes, const BoxJob* job, unsigned* h
 // Resident serving kernel of the group family on `grid` waves, and the
 // waves of it one CU can hold (occupancy).
 hipError_t launch_serve(const DevMech& m, const IntParams& prm, const ServeQueue& q, int grid, hipStream_t stream);
-int serve_waves_per_cu(const DevMech& m, bool f32);
+int serve_waves_per_cu(const DevMech& m, bool f32, int ir_max);
 // Zero `count` unsigned words of device memory with a kernel (no memset node).
 hipError_t launch_zero_u32(unsigned* p, int count, hipStream_t stream);
 

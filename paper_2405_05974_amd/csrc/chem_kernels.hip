@@ -1502,12 +1502,10 @@ hipError_t launch_serve_np(const DevMech& m, const IntParams& prm, const ServeQu
   return hipGetLastError();
 }
 
-// (sized with the FP32 rows kept apart from the FP64 ones: an upper bound of
-// the LDS the launch takes)
 template <int NP>
-int serve_waves_np(const DevMech& m, bool f32) {
+int serve_waves_np(const DevMech& m, bool f32, int ir_max) {
   int blocks = 0;
-  const size_t lds = integrate_lds_bytes(NP, m.N, f32);
+  const size_t lds = integrate_lds_bytes(NP, m.N, f32, f32 && NP == kWave && ir_max == 0);
   if constexpr (NP == kWave) {
     if (m.N <= kNarrowCols) {
       const hipError_t e =
@@ -1532,11 +1530,11 @@ hipError_t launch_serve(const DevMech& m, const IntParams& prm, const ServeQueue
   }
 }
 
-int serve_waves_per_cu(const DevMech& m, bool f32) {
+int serve_waves_per_cu(const DevMech& m, bool f32, int ir_max) {
   switch (m.np_width) {
-    case 16: return serve_waves_np<16>(m, f32);
-    case 32: return serve_waves_np<32>(m, f32);
-    case 64: return serve_waves_np<64>(m, f32);
+    case 16: return serve_waves_np<16>(m, f32, ir_max);
+    case 32: return serve_waves_np<32>(m, f32, ir_max);
+    case 64: return serve_waves_np<64>(m, f32, ir_max);
     default: return 1;
   }
 }

@@ -316,7 +316,7 @@ bool key_channel(chem_server* s, Channel& c, Request* r) {
   c.lpc = r->lpc;
   c.cpt = r->cpt;
   const int waves = c.lpc ? chemgpu::lpc_serve_waves_per_cu(c.m->lpc_serve)
-                          : chemgpu::serve_waves_per_cu(c.m->dev, c.m->lu_fp32 != 0);
+                          : chemgpu::serve_waves_per_cu(c.m->dev, c.m->lu_fp32 != 0, c.m->ir_max);
   c.grid = std::max(1, waves) * s->n_cu;
   // a fresh tile count: the claim counter back to zero (SDMA copy of a pinned
   // zero, ordered before the next launch on this stream)
