@@ -203,11 +203,10 @@ struct Shared {
   double* C;      // [64] concentrations (mol/cm^3)
   double* G;      // [64] G_k/(R T)
   double* H;      // [64] H_k, J/mol
-  double* W;      // [64] molecular weights (written once per kernel)
-  double* iW;     // [64] 1/W_c for species columns, 0 for the T and padding columns
-  double* isT;    // [64] 1 for the temperature column, else 0
+  double* iW;     // [64] 1/W_c for species columns, 0 for the T and padding columns (written once per kernel)
   double* rq;     // [3][64]: per species, sums of nu Q, nu dQ/dT and nu q0 over the reactions
-  double* prow;   // [2][64] pivot row, double-buffered
+  double* prow;   // [2][64] pivot row, double-buffered: rows 1-2 of rq, which a group never
+                  // uses while it factors (the sums are read into registers before)
   int* perm;      // [64] lane whose row holds pivot k
   float* F;       // [groups][rows][ldj] FP32 LU factors (mixed-precision option only)
   float* prow32;  // [2][64] FP32 pivot row
@@ -226,13 +225,11 @@ __device__ __forceinline__ Shared carve(double* smem, int NP, int N, bool f32 = 
   s.C = smem;
   s.G = s.C + kWave;
   s.H = s.G + kWave;
-  s.W = s.H + kWave;
-  s.iW = s.W + kWave;
-  s.isT = s.iW + kWave;
-  s.rq = s.isT + kWave;
-  s.prow = s.rq + 3 * kWave;
-  s.perm = reinterpret_cast<int*>(s.prow + 2 * kWave);
-  s.J = s.prow + 2 * kWave + kWave / 2;   // perm takes 64 ints = 32 doubles
+  s.iW = s.H + kWave;
+  s.rq = s.iW + kWave;
+  s.prow = s.rq + kWave;
+  s.perm = reinterpret_cast<int*>(s.rq + 3 * kWave);
+  s.J = s.rq + 3 * kWave + kWave / 2;   // perm takes 64 ints = 32 doubles
   const size_t jd = (size_t)(kWave / NP) * N * (NP + 1);
   if (f32 && f32_in_place) {
     s.F = reinterpret_cast<float*>(s.J);
@@ -249,7 +246,7 @@ __device__ __forceinline__ Shared carve(double* smem, int NP, int N, bool f32 = 
 size_t integrate_lds_bytes(int np_width, int N, bool f32, bool f32_in_place) {
   const int groups = kWave / np_width;
   const size_t jd = (size_t)groups * N * (np_width + 1);
-  const size_t doubles = 6 * kWave + 3 * kWave + 2 * kWave + kWave / 2 + jd;
+  const size_t doubles = 4 * kWave + 3 * kWave + kWave / 2 + jd;
   return doubles * sizeof(double) + (f32 && !f32_in_place ? (jd + 2 * kWave) * sizeof(float) : 0);
 }
 
@@ -542,7 +539,7 @@ __device__ __forceinline__ void rhs_eval(const DevMech& m, const Spc& sc, const 
         // species column c: (W_r/rho) dwdot_r/dY_c + (W_r wdot_r/rho) Wbar/W_c; T column: tT
         const double iWc = sh.iW[base + c];
         Jg[r * sh.ldj + c] = fac * ((Jg[r * sh.ldj + c] + ak) * rho * iWc - Wbar * iWc * AC) + fw * Wbar * iWc +
-                             sh.isT[base + c] * tT;
+                             ((c == S) ? 1.0 : 0.0) * tT;
       }
     }
     // temperature row, one column per lane (lanes beyond S write 0)
@@ -878,9 +875,7 @@ template <int NP>
 __device__ __forceinline__ void init_shared_constants(const DevMech& m, const Shared& sh) {
   const int lane = threadIdx.x & (kWave - 1);
   const int r = lane % NP;
-  sh.W[lane] = (r < m.S) ? m.W[r] : 1.0;
   sh.iW[lane] = (r < m.S) ? 1.0 / m.W[r] : 0.0;
-  sh.isT[lane] = (r == m.S) ? 1.0 : 0.0;
 }
 
 // Variable-order BDF over [0, dt] for the group's cell; the same decisions as
