@@ -34,7 +34,7 @@ def probe_figures():
     return json.load(open(path)) if os.path.exists(path) else {}
 
 
-def flops_survey_model(stats, S, R, c_exp, q):
+def flops_step_model(stats, S, R, c_exp, q):
     """Algorithmic FP64 flops of one launch by the per-step model
 
         F_step = n_N F_rhs + F_J + 2N^3/3 + n_N 2N^2 + 10 N q,
@@ -184,7 +184,7 @@ def main():
     lane = kname.startswith("chem_lpc_integrate")
     probes = probe_figures()
     c_exp = probes.get("c_exp_chexp" if lane else "c_exp_libexp", C_EXP_DEFAULT)
-    flops = flops_survey_model(st, m.n_species, m.n_reactions, c_exp, args.q_max)
+    flops = flops_step_model(st, m.n_species, m.n_reactions, c_exp, args.q_max)
     flops_item = flops_itemised_model(st, m.n_species, m.n_reactions, n_tb, n_fo)
     achieved = flops / (k_ms * 1e-3) / 1e12
     prof = measured_profile("chem_lpc_integrate") if (lane and args.config == 2 and shape == (256, 64, 64)) else None
