@@ -523,7 +523,7 @@ def bench_boxes(args, torch, dev, chem, synth):
     boxes = synth.amr_boxes(m, args.n_boxes, synth.config_seed(4), max_cells=args.max_box_cells)
     gm = chem.Mechanism(m.to_text())
     gm.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32), kernel=KERNEL_CODES[args.kernel],
-                   jac_reuse=int(args.jac_reuse), progress=20)
+                   jac_reuse=int(args.jac_reuse), progress=20, ir_max=args.ir_max)
     src = [(torch.tensor(b.T, device=dev), torch.tensor(b.Y, device=dev), b.dt) for b in boxes]
     work = [(t.clone(), y.clone(), dt) for t, y, dt in src]
     sample_T = torch.cat([t[: min(256, t.numel())] for t, _, _ in src[:8]])
@@ -666,7 +666,7 @@ def bench_serve(args, torch, dev, chem, synth):
         # stays on the lane-per-cell kernels, which keep the whole 11x11 matrix in FP64 registers
         lane = h.N <= LANE_MAX_N
         h.set_options(q_max=args.q_max, lu_fp32=int(args.lu_fp32 and not lane), jac_reuse=int(args.jac_reuse),
-                      kernel=KERNEL_CODES[args.kernel] if lane or args.kernel != "lane" else 0)
+                      kernel=KERNEL_CODES[args.kernel] if lane or args.kernel != "lane" else 0, ir_max=args.ir_max)
     arrivals = synth.poisson_trace(1005, args.rate, args.duration)
     pick = (np.random.default_rng(1005).random(arrivals.size) < args.mix).astype(int)
     srv = chem.Server(int(args.budget_gb * (1 << 30)), streams=4)
